@@ -1,0 +1,166 @@
+"""Benchmark of the HOTRG coarse-graining path on one MI355X.
+
+Workload: 2D Ising at T_c = 2/ln(1+sqrt 2), D_cut = 64, 30 directional
+coarse-graining steps (2^15 x 2^15 sites), synthetic (closed-form Boltzmann
+weights, no dataset).  One bench *step* is one whole run through the C ABI
+(hotrg_run: initial tensor, 30 directional steps, periodic trace), inputs
+built on the host inside the call.  `value` is directional coarse-graining
+steps per second over the timed runs.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec fp64|fp32|bf16x3]
+                    [--no-cpu-baseline]
+
+Prints one JSON line.  The dominant kernel is the D^7 contraction (C2);
+its average duration over the steady-state steps of the timed runs comes
+from HIP events recorded on the library's stream around each phase.
+"""
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "HOTRG steps/s + TFLOP/s at D=64 (mixed vs FP64), ln Z/N error, p50/p99 latency"
+BETA_C = math.log(1.0 + math.sqrt(2.0)) / 2.0
+ONSAGER_TC = math.log(2.0) / 2.0 + 2.0 * 0.915965594177219015054603514932384110774 / math.pi
+PEAKS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}  # TFLOP/s, dense MFMA, MI355X
+DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--d-cut", type=int, default=64)
+    ap.add_argument("--n-steps", type=int, default=30)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(d_cut):
+    """The oracle on the host cores: one steady-state directional step at
+    dims (d_cut, d_cut, d_cut) of the same Ising run (the warm-up steps that
+    produce its input are not timed)."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    from oracle import hotrg, tensors
+
+    T = tensors.ising(BETA_C)
+    T = T / np.abs(T).max()
+    k = 0
+    while not (T.shape[0] == d_cut and T.shape[1] == d_cut):
+        Tt, _, _, _ = hotrg.directional_step(T, d_cut)
+        T = hotrg.rotate(Tt)
+        T = T / np.abs(T).max()
+        k += 1
+        if k > 12:
+            raise RuntimeError("steady state not reached")
+    t0 = time.perf_counter()
+    Tt, _, _, _ = hotrg.directional_step(T, d_cut)
+    T = hotrg.rotate(Tt)
+    T = T / np.abs(T).max()
+    dt = time.perf_counter() - t0
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    from paper_2306_00358_amd.flops import step_flops
+
+    f = step_flops(d_cut, d_cut, d_cut)["total"]
+    return {"value": 1.0 / dt, "unit": "steps/s", "cores": threads, "kind": "oracle",
+            "sample": "one steady-state directional step (dims %d,%d,%d; step %d of the T_c run), "
+                      "numpy/OpenBLAS FP64, %.1f s, %.3f TFLOP/s" % (d_cut, d_cut, d_cut, k + 1, dt,
+                                                                     f / dt / 1e12)}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d, WORLD_SIZE %d)" % (args.gpus, world), file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2306_00358_amd import Context, hotrg_run, make_opts, model_params
+    from paper_2306_00358_amd.flops import dims_schedule, step_flops
+
+    assert torch.cuda.is_available(), "no GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    ctx = Context(0)
+    params = model_params("ising", beta=BETA_C)
+    opts = make_opts(args.d_cut, args.n_steps, prec=args.prec, spec_len=0)
+    sched = dims_schedule(2, args.d_cut, args.n_steps)
+    flops_run = sum(step_flops(*d)["total"] for d in sched)
+
+    for _ in range(args.warmup):
+        hotrg_run(ctx, params, opts)
+    ctx.timings()  # discard
+    ctx.enable_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = [hotrg_run(ctx, params, opts) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ctx.enable_timing(False)
+    recs = ctx.timings()
+
+    steady = (args.d_cut, args.d_cut, args.d_cut)
+    c2 = [r["ms"] for r in recs if r["phase"] == "c2" and (r["dx"], r["dy"], r["d_new"]) == steady]
+    phase_ms = {}
+    for r in recs:
+        phase_ms[r["phase"]] = phase_ms.get(r["phase"], 0.0) + r["ms"] / args.steps
+    c2_ms = sum(c2) / len(c2) if c2 else float("nan")
+    c2_flop = step_flops(*steady)["c2"]
+    achieved = c2_flop / (c2_ms * 1e-3) / 1e12
+    peak = PEAKS[args.prec]
+
+    lnz = results[-1]["lnz_per_site"]
+    n_dir = args.n_steps * args.steps
+    out = {
+        "metric": METRIC,
+        "value": n_dir / elapsed,
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE[args.prec],
+        "data": "synthetic",
+        "config": {"workload": "2D Ising HOTRG at Tc, D_cut=%d, %d directional steps, %s contractions"
+                               % (args.d_cut, args.n_steps, args.prec),
+                   "d_cut": args.d_cut, "n_steps": args.n_steps, "prec": args.prec,
+                   "beta": BETA_C},
+        "tflops": flops_run * args.steps / elapsed / 1e12,
+        "lnz_per_site": lnz,
+        "rel_err_vs_onsager": abs(lnz - ONSAGER_TC) / ONSAGER_TC,
+        "phase_ms_per_run": phase_ms,
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "kernel": "C2 GEMM %dx%dx%d" % (args.d_cut**3, args.d_cut**2, args.d_cut**2),
+                     "kernel_ms": c2_ms, "launches": len(c2)},
+    }
+    golden = os.path.join(ROOT, "tests", "golden", "ising_d64.json")
+    if args.d_cut == 64 and args.n_steps <= 40 and os.path.exists(golden):
+        with open(golden) as f:
+            rec = json.load(f)["runs"][0]
+        ref = rec["steps"][args.n_steps - 1]["lnz_torus"]
+        out["rel_err_vs_oracle"] = abs(lnz - ref) / abs(ref)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.d_cut)
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

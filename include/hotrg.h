@@ -1,0 +1,190 @@
+/*
+ * hotrg.h -- C ABI of libhotrg.so: the HOTRG coarse-graining step on the 2D
+ * square lattice (arXiv 2306.00358, Sec. 2 and Fig. 1) on one AMD MI355X
+ * (gfx950) GPU.
+ *
+ * Plain C99.  No C++ types or exceptions cross this boundary.  Pointers are
+ * host pointers unless the argument is documented as a device pointer.
+ * Every function returns a hotrg_status; on error the outputs are left
+ * untouched and hotrg_last_error() returns a message (per calling thread).
+ *
+ * Site tensors are rank 4 with legs (left, up, right, down), stored
+ * row-major with the left leg slowest: T[l][u][r][d].  A *directional step*
+ * merges two vertically adjacent copies (first above second) and fuses the
+ * pair of left legs (second.left, first.left) -- and likewise the right
+ * pair -- into one leg of dimension D' = min(d_cut, Dx*Dx), where Dx is the
+ * left/right dimension and Dy the up/down dimension before the step.  After
+ * the step the legs are transposed, (l,u,r,d) -> (u,l,d,r), so the next step
+ * coarse-grains the orthogonal direction; two directional steps make one
+ * iteration of the paper, and K steps cover 2^K sites.
+ *
+ * Per step k the tensor is divided by n_k = max|T| and
+ *     ln Z / N = ln n_0 + sum_k 2^-k ln n_k + 2^-K ln sum_{i,j} T_K[i][j][i][j]
+ * (periodic boundary conditions, Sec. 2).  The environment eigensolver and
+ * this accumulation are always FP64; `prec` selects the arithmetic of the
+ * contractions only.
+ */
+#ifndef HOTRG_H
+#define HOTRG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HOTRG_OK = 0,
+  HOTRG_ERR_INVALID = 1,   /* bad argument: sizes, model, d_cut < 1, null pointer */
+  HOTRG_ERR_OOM = 2,       /* the request does not fit the context's HBM budget */
+  HOTRG_ERR_DEVICE = 3,    /* a HIP / rocSOLVER call failed */
+  HOTRG_ERR_NUMERIC = 4,   /* non-finite norm, eigensolver failure, trace <= 0 */
+  HOTRG_ERR_NOT_READY = 5, /* submitted request still running */
+  HOTRG_ERR_CANCELLED = 6  /* submitted request was cancelled */
+} hotrg_status;
+
+typedef enum {
+  HOTRG_ISING = 0, /* Ising, bond dimension 2 (Sec. 3.2) */
+  HOTRG_XY = 1,    /* classical XY, character expansion, |n| <= n_max (Sec. 3.1, Delta = 1) */
+  HOTRG_POTTS = 2, /* q-state Potts, Cholesky split of the bond weight (Sec. 3.3) */
+  HOTRG_RAW = 3    /* caller-supplied initial tensor */
+} hotrg_model;
+
+typedef enum {
+  HOTRG_FP64 = 0,   /* FP64 MFMA contractions */
+  HOTRG_FP32 = 1,   /* FP32 MFMA contractions, FP32 intermediates */
+  HOTRG_BF16X3 = 2  /* split-BF16, three products, FP32 accumulation */
+} hotrg_precision;
+
+typedef enum {
+  HOTRG_TRUNC_PLAIN = 0,   /* keep the first D' eigenvectors (the paper) */
+  HOTRG_TRUNC_MULTIPLET = 1 /* never split a cluster of eigenvalues closer than
+                               degen_tol * lambda_1 at the cut: the cluster is
+                               dropped whole and U is padded with zero columns */
+} hotrg_trunc;
+
+typedef struct {
+  int model;          /* hotrg_model */
+  double beta;        /* inverse temperature 1/T (k_B = 1) */
+  double J;           /* Ising coupling (J * beta >= 0); ignored otherwise */
+  int n_max;          /* XY: charges |n| <= n_max, bond dimension 2 n_max + 1 */
+  int q;              /* Potts: number of states, >= 2 */
+  const double* raw;  /* HOTRG_RAW: host array raw_dx*raw_dy*raw_dx*raw_dy,
+                         legs (l,u,r,d); copied during the call */
+  int raw_dx, raw_dy; /* HOTRG_RAW: left/right and up/down dimensions */
+} hotrg_model_params;
+
+typedef struct {
+  int d_cut;          /* kept bond dimension, >= 1 */
+  int n_steps;        /* directional steps for hotrg_run, >= 0 */
+  int prec;           /* hotrg_precision */
+  int trunc;          /* hotrg_trunc */
+  double degen_tol;   /* multiplet tolerance tau (relative to lambda_1) */
+  int spec_len;       /* spectrum values recorded per step (0: none) */
+} hotrg_opts;
+
+typedef struct {
+  int dx, dy;         /* dimensions before the step */
+  int d_new;          /* D' = min(d_cut, dx*dx) */
+  int kept;           /* columns of U that are not zero padding */
+  double log_norm;    /* ln n_k */
+  double trunc_err;   /* 1 - sum_{m<=kept} lambda_m / trace(M) */
+  double cut_gap;     /* (lambda_{D'} - lambda_{D'+1}) / lambda_1; -1 when nothing is cut */
+  double lnz_torus;   /* ln Z / N of the 2^k-site torus after this step */
+} hotrg_step_info;
+
+typedef struct {
+  double lnz_per_site;     /* ln Z / N */
+  int n_steps;             /* steps done */
+  hotrg_step_info* steps;  /* caller-owned array of n_steps entries, or NULL */
+  double* spectra;         /* caller-owned [n_steps][spec_len] lambda/lambda_1
+                              descending (zero past dx*dx), or NULL */
+  double seconds;          /* wall time of the call */
+} hotrg_result;
+
+typedef struct hotrg_ctx hotrg_ctx;
+typedef struct hotrg_state hotrg_state;
+
+/* Context on one GPU.  `hip_stream` is a hipStream_t to run on (borrowed, may
+ * be NULL for a stream of the context's own).  `hbm_budget` bounds the
+ * device memory the context may hold, in bytes (0: no bound).  The context
+ * owns all device buffers and states it creates.  Not thread-safe except for
+ * the submit/poll/wait/cancel family. */
+hotrg_status hotrg_ctx_create(int device, void* hip_stream, size_t hbm_budget, hotrg_ctx** out);
+void hotrg_ctx_destroy(hotrg_ctx* ctx);
+const char* hotrg_last_error(void);
+size_t hotrg_ctx_bytes_in_use(const hotrg_ctx* ctx);
+
+/* a0: build the initial tensor of `params` in FP64 on the host, upload it
+ * and divide it by n_0 = max|T0| (Sec. 3: Ising, XY, Potts tensors).  The
+ * state records ln n_0 and is owned by ctx until hotrg_state_free. */
+hotrg_status hotrg_init_tensor(hotrg_ctx* ctx, const hotrg_model_params* params,
+                               int prec, hotrg_state** out);
+
+/* a1..a7: one directional coarse-graining step (Sec. 2, Fig. 1): environment
+ * M, FP64 eigendecomposition, projector U, the three contractions, the
+ * transposition of legs and the normalisation.  `info` (may be NULL)
+ * receives the step record and `spectrum` (host, may be NULL) the first
+ * opts->spec_len values of lambda/lambda_1; either being non-NULL makes the
+ * call wait for the GPU.  opts->n_steps is ignored. */
+hotrg_status hotrg_step(hotrg_ctx* ctx, hotrg_state* st, const hotrg_opts* opts,
+                        hotrg_step_info* info, double* spectrum);
+
+/* a8: ln Z / N from the steps done so far and the periodic trace. */
+hotrg_status hotrg_finish(hotrg_ctx* ctx, hotrg_state* st, double* lnz_per_site);
+
+/* Copy the current (normalised) tensor to the host.  `dims` receives
+ * (dx, dy); `cap` is the capacity of `host` in doubles; `acc` receives
+ * ln n_0 + sum_k 2^-k ln n_k and `k` the number of steps done. */
+hotrg_status hotrg_state_export(hotrg_ctx* ctx, const hotrg_state* st, double* host, size_t cap,
+                                int dims[2], double* acc, int* k);
+void hotrg_state_free(hotrg_ctx* ctx, hotrg_state* st);
+
+/* a0..a8: init, opts->n_steps directional steps, finish; one host wait at the
+ * end.  result->steps / result->spectra are filled when non-NULL. */
+hotrg_status hotrg_run(hotrg_ctx* ctx, const hotrg_model_params* params, const hotrg_opts* opts,
+                       hotrg_result* result);
+
+/* ---- per-phase timing (HIP events on the context's stream) -------------
+ * When enabled, every phase of every step is bracketed by HIP events;
+ * hotrg_ctx_timings waits for the stream, copies up to `cap` records into
+ * `out` (host) and clears the list.  It returns the number of records
+ * copied, or -1 on error. */
+enum {
+  HOTRG_PHASE_ENV = 0,   /* a1+a2: environment halves, combine, symmetrise */
+  HOTRG_PHASE_EIGH = 1,  /* a3: FP64 eigendecomposition of M */
+  HOTRG_PHASE_PROJ = 2,  /* a3: spectrum, truncation, projector layouts */
+  HOTRG_PHASE_C1 = 3,    /* a4 */
+  HOTRG_PHASE_C2 = 4,    /* a5: the O(D^7) contraction */
+  HOTRG_PHASE_C3 = 5,    /* a6 with max|T~| */
+  HOTRG_PHASE_NORM = 6   /* a7: log-norm, trace, next operands */
+};
+typedef struct {
+  int step;   /* 1-based step index within its state */
+  int phase;  /* HOTRG_PHASE_* */
+  int dx, dy, d_new;
+  float ms;   /* elapsed time between the phase's events */
+} hotrg_phase_time;
+hotrg_status hotrg_ctx_enable_timing(hotrg_ctx* ctx, int on);
+int hotrg_ctx_timings(hotrg_ctx* ctx, hotrg_phase_time* out, int cap);
+
+/* ---- primitive contractions on caller device buffers (same kernels) -----
+ * All pointers are device pointers of FP64 arrays, row-major.  They run on
+ * the context's stream and return without waiting for it. */
+
+/* a1+a2: M[(i,j),(k,l)] = sum T[j,a,b,e] T[i,e,c,d] T[l,a,b,f] T[k,f,c,d]
+ * (Sec. 2), T of shape (dx,dy,dx,dy), M of shape (dx*dx, dx*dx). */
+hotrg_status hotrg_environment(hotrg_ctx* ctx, const double* T, int dx, int dy, double* M);
+
+/* a4..a6: Tt[i,j,k,l] = sum U[a,b,i] T[b,j,d,c] T[a,c,e,l] U[e,d,k] (Sec. 2),
+ * T (dx,dy,dx,dy), U (dx,dx,dn), Tt (dn,dy,dn,dy); *max_abs (device,
+ * may be NULL) receives max|Tt|. */
+hotrg_status hotrg_coarse(hotrg_ctx* ctx, const double* T, const double* U, int dx, int dy, int dn,
+                          double* Tt, double* max_abs);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HOTRG_H */

@@ -111,6 +111,16 @@ def coarse_tensor(T, U3):
     return Tt.transpose(0, 1, 3, 2)                      # (i, j, k, l)
 
 
+def coarse_tensor_slice(T, U3, i, k):
+    """T~[i, :, k, :] of ``coarse_tensor`` for one pair (i, k), at a cost of
+    O(D^5): L[a,j,d,c] = sum_b U[a,b,i] T[b,j,d,c],
+    R[a,c,l,d] = sum_e T[a,c,e,l] U[e,d,k], T~[i,j,k,l] = sum_{a,c,d} L R.
+    Used to check single outputs of large coarse tensors."""
+    L = np.tensordot(U3[:, :, i], T, axes=([1], [0]))          # (a, j, d, c)
+    R = np.tensordot(T, U3[:, :, k], axes=([2], [0]))          # (a, c, l, d)
+    return np.tensordot(L, R, axes=([0, 2, 3], [0, 3, 1]))     # (j, l)
+
+
 def directional_step(T, d_cut, trunc="plain", tau=1e-10):
     """One directional coarse-graining: environment, projector, coarse
     tensor.  Returns (T~ with legs (l, u, r, d) of the merged pair,

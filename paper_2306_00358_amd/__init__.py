@@ -1,0 +1,15 @@
+"""HOTRG coarse-graining on AMD MI355X (gfx950): Python binding of libhotrg.so.
+
+The library (include/hotrg.h) runs the higher-order TRG step of
+arXiv 2306.00358 (Sec. 2) on one GPU: environment contractions and the three
+coarse contractions as MFMA GEMMs, the FP64 eigendecomposition of the
+environment, and FP64 log-norm accumulation.  This package only marshals
+arguments; see ``_lib`` for the calls.
+"""
+
+from ._lib import (  # noqa: F401
+    EXPORTS, HOTRG_BF16X3, HOTRG_FP32, HOTRG_FP64, HOTRG_ISING, HOTRG_POTTS, HOTRG_RAW,
+    HOTRG_TRUNC_MULTIPLET, HOTRG_TRUNC_PLAIN, HOTRG_XY, LIB_PATH, Context, HotrgError, State,
+    hotrg_coarse, hotrg_environment, hotrg_run, lib, make_opts, model_params,
+)
+from .flops import step_flops, run_flops, dims_schedule  # noqa: F401

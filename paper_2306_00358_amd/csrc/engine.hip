@@ -1,0 +1,716 @@
+// Host engine of libhotrg: contexts, device buffers, the directional step
+// and the C ABI of include/hotrg.h (arXiv 2306.00358, Sec. 2, Fig. 1).
+//
+// One step on one HIP stream, no host wait inside:
+//   environment halves  A2 = X_b X_b^T, A1 = X_t X_t^T      (MFMA GEMM)
+//   environment combine M = A2' A1'^T, symmetrised          (MFMA GEMM)
+//   eigendecomposition of M in FP64                          (rocSOLVER dsyevd)
+//   spectrum, truncation error, cut gap, projector U          (single-block kernels)
+//   C1: X1 = U T,  C2: X2 = X1 T,  C3: T~ = X2 U, max|T~|     (MFMA GEMMs)
+//   ln n_k accumulation and torus trace                       (single block)
+//   operands of the next step: legs transposed, divided by n_k
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/hotrg.h"
+#include "internal.h"
+
+namespace hotrg {
+std::vector<double> ising_tensor(double beta, double J);
+std::vector<double> xy_tensor(double beta, int n_max);
+std::vector<double> potts_tensor(double beta, int q);
+}  // namespace hotrg
+
+using namespace hotrg;
+
+static thread_local std::string g_err;
+
+namespace {
+
+struct Error {
+  hotrg_status st;
+  std::string msg;
+};
+
+[[noreturn]] void fail(hotrg_status st, const std::string& msg) { throw Error{st, msg}; }
+
+#define HIPCHK(x)                                                                      \
+  do {                                                                                 \
+    hipError_t e_ = (x);                                                               \
+    if (e_ != hipSuccess) fail(HOTRG_ERR_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+struct Buf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct hotrg_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  size_t budget = 0;
+  size_t in_use = 0;
+  rocblas_handle blas = nullptr;
+  // step workspace, grown on demand
+  Buf A1, A2, M, W, E, Ucan, U1, U3, X1, X2, Tt, scal;
+  // scal layout: [0] maxbits (u64), [1] info (int), [2] kept (int), [3] finish out (double)
+  // per-phase timing
+  bool timing = false;
+  struct Mark {
+    int step, phase, dx, dy, dn;
+    hipEvent_t a, b;
+  };
+  std::vector<Mark> marks;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t open_ev = nullptr;
+  int open_phase = -1, m_step = 0, m_dx = 0, m_dy = 0, m_dn = 0;
+};
+
+struct hotrg_state {
+  int prec = HOTRG_FP64;
+  int dx = 0, dy = 0, k = 0;
+  Buf Tn, Xt, Tp;      // operands of the next step (normalised)
+  Buf acc;             // device double: ln n_0 + sum_k 2^-k ln n_k
+  Buf recs;            // device: 5 doubles per step
+  Buf spec;            // device spectra, spec_cap doubles per step
+  int rec_cap = 0, spec_len = 0;
+};
+
+namespace {
+
+void ctx_free(hotrg_ctx* c, Buf& b) {
+  if (b.p) {
+    hipFree(b.p);
+    c->in_use -= b.bytes;
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+}
+
+// Make `b` hold at least `bytes`, keeping the HBM budget.  Growing frees the
+// old buffer first (its contents are not kept).
+void ensure(hotrg_ctx* c, Buf& b, size_t bytes) {
+  if (bytes == 0) bytes = 8;
+  if (b.bytes >= bytes) return;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  ctx_free(c, b);
+  if (c->budget && c->in_use + bytes > c->budget)
+    fail(HOTRG_ERR_OOM, "device memory budget exceeded: need " + std::to_string(bytes) +
+                            " more bytes, " + std::to_string(c->in_use) + " of " +
+                            std::to_string(c->budget) + " in use");
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess)
+    fail(e == hipErrorOutOfMemory ? HOTRG_ERR_OOM : HOTRG_ERR_DEVICE,
+         std::string("hipMalloc(") + std::to_string(bytes) + "): " + hipGetErrorString(e));
+  b.p = p;
+  b.bytes = bytes;
+  c->in_use += bytes;
+}
+
+// Grow while keeping the first `keep` bytes.
+void ensure_keep(hotrg_ctx* c, Buf& b, size_t bytes, size_t keep) {
+  if (b.bytes >= bytes) return;
+  Buf old = b;
+  b = Buf{};
+  try {
+    ensure(c, b, bytes);
+  } catch (...) {
+    b = old;
+    throw;
+  }
+  if (old.p) {
+    if (keep) HIPCHK(hipMemcpyAsync(b.p, old.p, keep, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    hipFree(old.p);
+    c->in_use -= old.bytes;
+  }
+}
+
+hipEvent_t get_event(hotrg_ctx* c) {
+  if (!c->pool.empty()) {
+    hipEvent_t e = c->pool.back();
+    c->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  HIPCHK(hipEventCreate(&e));
+  return e;
+}
+
+// Close the open phase (if any) and open `phase` (-1: just close).
+void mark(hotrg_ctx* c, int phase) {
+  if (!c->timing) return;
+  hipEvent_t e = get_event(c);
+  HIPCHK(hipEventRecord(e, c->stream));
+  if (c->open_phase >= 0)
+    c->marks.push_back({c->m_step, c->open_phase, c->m_dx, c->m_dy, c->m_dn, c->open_ev, e});
+  if (phase >= 0) {
+    // the closing event of one phase opens the next
+    c->open_ev = e;
+    c->open_phase = phase;
+  } else {
+    c->open_phase = -1;
+    c->open_ev = nullptr;
+  }
+}
+
+size_t esz(int prec) { return prec == HOTRG_FP64 ? 8 : 4; }
+
+void check_prec(int prec) {
+  if (prec != HOTRG_FP64 && prec != HOTRG_FP32 && prec != HOTRG_BF16X3)
+    fail(HOTRG_ERR_INVALID, "prec must be HOTRG_FP64, HOTRG_FP32 or HOTRG_BF16X3");
+}
+
+void check_opts(const hotrg_opts* o) {
+  if (!o) fail(HOTRG_ERR_INVALID, "opts is NULL");
+  if (o->d_cut < 1) fail(HOTRG_ERR_INVALID, "d_cut must be >= 1");
+  if (o->n_steps < 0) fail(HOTRG_ERR_INVALID, "n_steps must be >= 0");
+  if (o->trunc != HOTRG_TRUNC_PLAIN && o->trunc != HOTRG_TRUNC_MULTIPLET)
+    fail(HOTRG_ERR_INVALID, "trunc must be HOTRG_TRUNC_PLAIN or HOTRG_TRUNC_MULTIPLET");
+  if (o->trunc == HOTRG_TRUNC_MULTIPLET && !(o->degen_tol >= 0.0))
+    fail(HOTRG_ERR_INVALID, "degen_tol must be >= 0");
+  if (o->spec_len < 0) fail(HOTRG_ERR_INVALID, "spec_len must be >= 0");
+  check_prec(o->prec);
+}
+
+// Largest intermediate of a step with dims (dx, dy) and D' = dn, in elements.
+long long x_elems(int dx, int dy, int dn) { return (long long)dn * dx * dy * dx * dy; }
+
+void check_dims(int dx, int dy, int dn) {
+  long long n = (long long)dx * dx;
+  if (n > 16384) fail(HOTRG_ERR_INVALID, "dx*dx exceeds 16384 (environment matrix too large)");
+  if (x_elems(dx, dy, dn) > (1LL << 36)) fail(HOTRG_ERR_INVALID, "intermediate exceeds 2^36 elements");
+  if ((long long)dn * dy * dx > 0x7fffffffLL || (long long)dx * dy * dx > 0x7fffffffLL)
+    fail(HOTRG_ERR_INVALID, "GEMM dimension exceeds 2^31");
+}
+
+// FP64 operands of T (dims dx, dy) in the state: environment halves into M.
+void environment_f64(hotrg_ctx* c, const double* Tn, const double* Xt, int dx, int dy) {
+  const long long P = (long long)dx * dy;  // rows / cols of the halves
+  const long long n = (long long)dx * dx;
+  const long long K2 = (long long)dy * dy;
+  ensure(c, c->A1, (size_t)(P * P) * 8);
+  ensure(c, c->A2, (size_t)(P * P) * 8);
+  ensure(c, c->M, (size_t)(n * n) * 8);
+  // A2[(i,e),(k,f)] = sum_{c,d} T[i,e,c,d] T[k,f,c,d], stored as A2'[(i,k),(e,f)]
+  // rows (i,e): i -> dx*dy^2, e -> dy; cols (k,f): k -> dy^2, f -> 1
+  const OutMap o2 = omap2(dy, dx * K2, dy, dy, K2, 1);
+  gemm_f64(Tn, P, Tn, P, B_KCONTIG, (double*)c->A2.p, o2, (int)P, (int)P, (int)P, nullptr,
+           c->stream);
+  // A1[(j,e),(l,f)] = sum_{a,b} T[j,a,b,e] T[l,a,b,f] from Xt[(l,d),(u,r)], stored as A1'[(j,l),(e,f)]
+  gemm_f64(Xt, P, Xt, P, B_KCONTIG, (double*)c->A1.p, o2, (int)P, (int)P, (int)P, nullptr,
+           c->stream);
+  // M[(i,j),(k,l)] = sum_{e,f} A2'[(i,k),(e,f)] A1'[(j,l),(e,f)]: GEMM rows (i,k), cols (j,l)
+  // rows (i,k): i -> dx*n, k -> dx; cols (j,l): j -> n, l -> 1
+  const OutMap om = omap2(dx, dx * n, dx, dx, n, 1);
+  gemm_f64((const double*)c->A2.p, K2, (const double*)c->A1.p, K2, B_KCONTIG, (double*)c->M.p, om,
+           (int)n, (int)n, (int)K2, nullptr, c->stream);
+}
+
+// C1, C2, C3 in FP64: T~[i,j,k,l] (dims dn,dy,dn,dy) into c->Tt, max into scal.
+void coarse_f64(hotrg_ctx* c, const double* Tn, const double* Tp, const double* U1,
+                const double* U3, int dx, int dy, int dn, unsigned long long* maxbits) {
+  const long long X = x_elems(dx, dy, dn);
+  ensure(c, c->X1, (size_t)X * 8);
+  ensure(c, c->X2, (size_t)X * 8);
+  ensure(c, c->Tt, (size_t)dn * dy * dn * dy * 8);
+  const long long Q = (long long)dx * dy;
+  // C1: rows (i,a), cols (j,d,c) = j*(dx*dy) + (d*dy + c); K = b.
+  //     X1[(i,j,d),(a,c)] at ((i*dy + j)*dx + d)*Q + a*dy + c
+  //     rows (i,a): i -> dy*dx*Q, a -> dy; cols (j,d,c): j -> dx*Q, d -> Q, c -> 1
+  OutMap o1 = omap2(dx, (long long)dy * dx * Q, dy, 1, 0, 0);
+  o1.c1 = dx; o1.c2 = dy; o1.t0 = (long long)dx * Q; o1.t1 = Q; o1.t2 = 1;
+  mark(c, HOTRG_PHASE_C1);
+  gemm_f64(U1, dx, Tn, (long long)dy * dx * dy, B_NCONTIG, (double*)c->X1.p, o1, dn * dx,
+           dy * dx * dy, dx, nullptr, c->stream);
+  // C2: rows (i,j,d) = (ij)*dx + d, cols (l,e) = l*dx + e; K = (a,c).
+  //     X2[(i,j,l),(d,e)] at ((ij)*dy + l)*dx*dx + d*dx + e
+  const long long n = (long long)dx * dx;
+  //     rows (ij,d): ij -> dy*n, d -> dx; cols (l,e): l -> n, e -> 1
+  const OutMap o2 = omap2(dx, (long long)dy * n, dx, dx, n, 1);
+  mark(c, HOTRG_PHASE_C2);
+  gemm_f64((const double*)c->X1.p, Q, Tp, Q, B_NCONTIG, (double*)c->X2.p, o2, dn * dy * dx,
+           (int)Q, (int)Q, nullptr, c->stream);
+  // C3: rows (i,j,l) = (ij)*dy + l, cols k; K = (d,e).
+  //     T~[i,j,k,l] at ((ij)*dn + k)*dy + l
+  mark(c, HOTRG_PHASE_C3);
+  HIPCHK(hipMemsetAsync(maxbits, 0, 8, c->stream));
+  //     rows (ij,l): ij -> dn*dy, l -> 1; cols k -> dy
+  const OutMap o3 = omap2(dy, (long long)dn * dy, 1, 1, dy, 0);
+  gemm_f64((const double*)c->X2.p, n, U3, dn, B_NCONTIG, (double*)c->Tt.p, o3, dn * dy * dy, dn,
+           (int)n, maxbits, c->stream);
+}
+
+hotrg_state* new_state(hotrg_ctx* c, const std::vector<double>& T0, int dx, int dy, int prec) {
+  for (double v : T0)
+    if (!std::isfinite(v)) fail(HOTRG_ERR_NUMERIC, "initial tensor has a non-finite element");
+  auto* st = new hotrg_state();
+  try {
+    st->prec = prec;
+    st->dx = dx;
+    st->dy = dy;
+    const size_t ne = T0.size();
+    ensure(c, st->acc, 8);
+    ensure(c, c->scal, 64);
+    // upload through the Tt workspace as FP64
+    ensure(c, c->Tt, ne * 8);
+    HIPCHK(hipMemcpyAsync(c->Tt.p, T0.data(), ne * 8, hipMemcpyHostToDevice, c->stream));
+    unsigned long long* mb = (unsigned long long*)c->scal.p;
+    HIPCHK(hipMemsetAsync(mb, 0, 8, c->stream));
+    launch_maxabs(c->Tt.p, (long long)ne, false, mb, c->stream);
+    launch_init_acc(mb, (double*)st->acc.p, c->stream);
+    ensure(c, st->Tn, ne * esz(prec));
+    ensure(c, st->Xt, ne * esz(prec));
+    ensure(c, st->Tp, ne * esz(prec));
+    launch_prep(c->Tt.p, false, false, dx, dy, mb, st->Tn.p, st->Xt.p, st->Tp.p,
+                prec != HOTRG_FP64, c->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+  } catch (...) {
+    hotrg_state_free(c, st);
+    throw;
+  }
+  return st;
+}
+
+void do_step(hotrg_ctx* c, hotrg_state* st, const hotrg_opts* o) {
+  const int dx = st->dx, dy = st->dy;
+  const int n = dx * dx;
+  const int dn = o->d_cut < n ? o->d_cut : n;
+  check_dims(dx, dy, dn);
+  if (st->prec != HOTRG_FP64) fail(HOTRG_ERR_INVALID, "reduced precision not built yet");
+  const int k = st->k + 1;
+  // per-step records and spectra
+  if (k > st->rec_cap) {
+    int cap = st->rec_cap ? 2 * st->rec_cap : 64;
+    while (cap < k) cap *= 2;
+    ensure_keep(c, st->recs, (size_t)cap * 5 * 8, (size_t)st->rec_cap * 5 * 8);
+    if (st->spec_len)
+      ensure_keep(c, st->spec, (size_t)cap * st->spec_len * 8, (size_t)st->rec_cap * st->spec_len * 8);
+    st->rec_cap = cap;
+  }
+  if (o->spec_len != st->spec_len) {
+    if (st->k > 0 && st->spec_len != 0)
+      fail(HOTRG_ERR_INVALID, "spec_len must not change between steps of one state");
+    st->spec_len = o->spec_len;
+    if (st->spec_len) ensure(c, st->spec, (size_t)st->rec_cap * st->spec_len * 8);
+  }
+  double* rec = (double*)st->recs.p + 5 * (size_t)(k - 1);
+  double* spec = st->spec_len ? (double*)st->spec.p + (size_t)(k - 1) * st->spec_len : nullptr;
+  ensure(c, c->scal, 64);
+  unsigned long long* mb = (unsigned long long*)c->scal.p;
+  int* info = (int*)((char*)c->scal.p + 8);
+  int* kept = (int*)((char*)c->scal.p + 16);
+
+  c->m_step = k;
+  c->m_dx = dx;
+  c->m_dy = dy;
+  c->m_dn = dn;
+  mark(c, HOTRG_PHASE_ENV);
+  // a1, a2: environment
+  environment_f64(c, (const double*)st->Tn.p, (const double*)st->Xt.p, dx, dy);
+  launch_symmetrize((double*)c->M.p, n, c->stream);
+  // a3: FP64 eigendecomposition, spectrum and projector
+  ensure(c, c->W, (size_t)n * 8);
+  ensure(c, c->E, (size_t)n * 8);
+  mark(c, HOTRG_PHASE_EIGH);
+  rocblas_status rs = rocsolver_dsyevd(c->blas, rocblas_evect_original, rocblas_fill_lower, n,
+                                       (double*)c->M.p, n, (double*)c->W.p, (double*)c->E.p, info);
+  if (rs != rocblas_status_success)
+    fail(HOTRG_ERR_DEVICE, "rocsolver_dsyevd failed with status " + std::to_string((int)rs));
+  mark(c, HOTRG_PHASE_PROJ);
+  launch_spectrum((const double*)c->W.p, n, dn, o->trunc, o->degen_tol, st->spec_len, spec, rec,
+                  kept, c->stream);
+  ensure(c, c->Ucan, (size_t)n * dn * 8);
+  ensure(c, c->U1, (size_t)n * dn * 8);
+  ensure(c, c->U3, (size_t)n * dn * 8);
+  launch_isometry((const double*)c->M.p, n, dn, kept, (double*)c->Ucan.p, c->stream);
+  launch_layout_u((const double*)c->Ucan.p, dx, dn, c->U1.p, c->U3.p, false, c->stream);
+  // a4..a6: the three contractions, max|T~|
+  coarse_f64(c, (const double*)st->Tn.p, (const double*)st->Tp.p, (const double*)c->U1.p,
+             (const double*)c->U3.p, dx, dy, dn, mb);
+  // a7: ln n_k, torus estimate; operands of the next step (legs transposed)
+  mark(c, HOTRG_PHASE_NORM);
+  launch_norm(mb, c->Tt.p, false, dn, dy, std::ldexp(1.0, -k), (double*)st->acc.p, rec, c->stream);
+  const int ndx = dy, ndy = dn;
+  const size_t ne = (size_t)ndx * ndy * ndx * ndy;
+  ensure_keep(c, st->Tn, ne * 8, 0);
+  ensure_keep(c, st->Xt, ne * 8, 0);
+  ensure_keep(c, st->Tp, ne * 8, 0);
+  launch_prep(c->Tt.p, false, true, ndx, ndy, mb, st->Tn.p, st->Xt.p, st->Tp.p, false, c->stream);
+  mark(c, -1);
+  HIPCHK(hipGetLastError());
+  st->dx = ndx;
+  st->dy = ndy;
+  st->k = k;
+}
+
+void fetch_info(hotrg_ctx* c, hotrg_state* st, int first, int count, const int* dims_dx,
+                hotrg_step_info* out, double* spectra) {
+  // dims are reconstructed by the caller; records come from the device
+  std::vector<double> r((size_t)count * 5);
+  if (count == 0) return;
+  HIPCHK(hipMemcpyAsync(r.data(), (double*)st->recs.p + 5 * (size_t)first, r.size() * 8,
+                        hipMemcpyDeviceToHost, c->stream));
+  if (spectra && st->spec_len)
+    HIPCHK(hipMemcpyAsync(spectra, (double*)st->spec.p + (size_t)first * st->spec_len,
+                          (size_t)count * st->spec_len * 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (out)
+    for (int i = 0; i < count; ++i) {
+      out[i].log_norm = r[5 * i + 0];
+      out[i].trunc_err = r[5 * i + 1];
+      out[i].cut_gap = r[5 * i + 2];
+      out[i].lnz_torus = r[5 * i + 3];
+      out[i].kept = (int)r[5 * i + 4];
+    }
+  (void)dims_dx;
+}
+
+void check_info(hotrg_ctx* c) {
+  int info = 0;
+  HIPCHK(hipMemcpyAsync(&info, (char*)c->scal.p + 8, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (info != 0) fail(HOTRG_ERR_NUMERIC, "eigensolver did not converge (info " + std::to_string(info) + ")");
+}
+
+std::vector<double> build_tensor(const hotrg_model_params* p, int* dx, int* dy) {
+  if (!p) fail(HOTRG_ERR_INVALID, "params is NULL");
+  try {
+    switch (p->model) {
+      case HOTRG_ISING:
+        *dx = *dy = 2;
+        return ising_tensor(p->beta, p->J);
+      case HOTRG_XY:
+        *dx = *dy = 2 * p->n_max + 1;
+        return xy_tensor(p->beta, p->n_max);
+      case HOTRG_POTTS:
+        *dx = *dy = p->q;
+        return potts_tensor(p->beta, p->q);
+      case HOTRG_RAW: {
+        if (!p->raw || p->raw_dx < 1 || p->raw_dy < 1 || p->raw_dx > 128 || p->raw_dy > 16384)
+          fail(HOTRG_ERR_INVALID, "raw tensor: need raw != NULL, 1 <= raw_dx <= 128, raw_dy >= 1");
+        *dx = p->raw_dx;
+        *dy = p->raw_dy;
+        size_t ne = (size_t)p->raw_dx * p->raw_dy * p->raw_dx * p->raw_dy;
+        return std::vector<double>(p->raw, p->raw + ne);
+      }
+      default:
+        fail(HOTRG_ERR_INVALID, "unknown model");
+    }
+  } catch (const std::invalid_argument& e) {
+    fail(HOTRG_ERR_INVALID, e.what());
+  }
+}
+
+template <class F>
+hotrg_status guard(F&& f) {
+  try {
+    f();
+    return HOTRG_OK;
+  } catch (const Error& e) {
+    g_err = e.msg;
+    return e.st;
+  } catch (const std::bad_alloc&) {
+    g_err = "host allocation failed";
+    return HOTRG_ERR_OOM;
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return HOTRG_ERR_DEVICE;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hotrg_last_error(void) { return g_err.c_str(); }
+
+hotrg_status hotrg_ctx_create(int device, void* hip_stream, size_t hbm_budget, hotrg_ctx** out) {
+  return guard([&] {
+    if (!out) fail(HOTRG_ERR_INVALID, "out is NULL");
+    int n = 0;
+    HIPCHK(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) fail(HOTRG_ERR_INVALID, "no such device");
+    HIPCHK(hipSetDevice(device));
+    auto* c = new hotrg_ctx();
+    c->device = device;
+    c->budget = hbm_budget;
+    if (hip_stream) {
+      c->stream = (hipStream_t)hip_stream;
+    } else {
+      hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+      if (e != hipSuccess) {
+        delete c;
+        fail(HOTRG_ERR_DEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+      }
+      c->own_stream = true;
+    }
+    if (rocblas_create_handle(&c->blas) != rocblas_status_success) {
+      if (c->own_stream) hipStreamDestroy(c->stream);
+      delete c;
+      fail(HOTRG_ERR_DEVICE, "rocblas_create_handle failed");
+    }
+    rocblas_set_stream(c->blas, c->stream);
+    *out = c;
+  });
+}
+
+void hotrg_ctx_destroy(hotrg_ctx* c) {
+  if (!c) return;
+  hipSetDevice(c->device);
+  hipStreamSynchronize(c->stream);
+  Buf* bufs[] = {&c->A1, &c->A2, &c->M, &c->W, &c->E, &c->Ucan, &c->U1, &c->U3,
+                 &c->X1, &c->X2, &c->Tt, &c->scal};
+  for (Buf* b : bufs) ctx_free(c, *b);
+  for (auto& m : c->marks) {
+    c->pool.push_back(m.a);
+    c->pool.push_back(m.b);
+  }
+  std::sort(c->pool.begin(), c->pool.end());
+  c->pool.erase(std::unique(c->pool.begin(), c->pool.end()), c->pool.end());
+  for (hipEvent_t e : c->pool) hipEventDestroy(e);
+  if (c->blas) rocblas_destroy_handle(c->blas);
+  if (c->own_stream) hipStreamDestroy(c->stream);
+  delete c;
+}
+
+size_t hotrg_ctx_bytes_in_use(const hotrg_ctx* c) { return c ? c->in_use : 0; }
+
+hotrg_status hotrg_init_tensor(hotrg_ctx* c, const hotrg_model_params* params, int prec,
+                               hotrg_state** out) {
+  return guard([&] {
+    if (!c || !out) fail(HOTRG_ERR_INVALID, "ctx/out is NULL");
+    check_prec(prec);
+    HIPCHK(hipSetDevice(c->device));
+    int dx = 0, dy = 0;
+    std::vector<double> T0 = build_tensor(params, &dx, &dy);
+    *out = new_state(c, T0, dx, dy, prec);
+  });
+}
+
+hotrg_status hotrg_step(hotrg_ctx* c, hotrg_state* st, const hotrg_opts* o, hotrg_step_info* info,
+                        double* spectrum) {
+  return guard([&] {
+    if (!c || !st) fail(HOTRG_ERR_INVALID, "ctx/state is NULL");
+    check_opts(o);
+    HIPCHK(hipSetDevice(c->device));
+    const int dx = st->dx, dy = st->dy;
+    do_step(c, st, o);
+    if (info || spectrum) {
+      check_info(c);
+      hotrg_step_info tmp;
+      double* sp = nullptr;
+      std::vector<double> spv;
+      if (spectrum && st->spec_len) {
+        spv.resize(st->spec_len);
+        sp = spv.data();
+      }
+      fetch_info(c, st, st->k - 1, 1, nullptr, &tmp, sp);
+      tmp.dx = dx;
+      tmp.dy = dy;
+      tmp.d_new = st->dy;
+      if (info) *info = tmp;
+      if (spectrum && sp) std::memcpy(spectrum, sp, spv.size() * 8);
+    }
+  });
+}
+
+hotrg_status hotrg_finish(hotrg_ctx* c, hotrg_state* st, double* lnz) {
+  return guard([&] {
+    if (!c || !st || !lnz) fail(HOTRG_ERR_INVALID, "ctx/state/out is NULL");
+    HIPCHK(hipSetDevice(c->device));
+    ensure(c, c->scal, 64);
+    double* outp = (double*)((char*)c->scal.p + 24);
+    launch_finish(st->Tn.p, st->prec != HOTRG_FP64, st->dx, st->dy, std::ldexp(1.0, -st->k),
+                  (const double*)st->acc.p, outp, c->stream);
+    HIPCHK(hipGetLastError());
+    double v = 0;
+    HIPCHK(hipMemcpyAsync(&v, outp, 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (st->k > 0) check_info(c);
+    if (!std::isfinite(v)) fail(HOTRG_ERR_NUMERIC, "non-finite ln Z (norm or trace <= 0)");
+    *lnz = v;
+  });
+}
+
+hotrg_status hotrg_state_export(hotrg_ctx* c, const hotrg_state* st, double* host, size_t cap,
+                                int dims[2], double* acc, int* k) {
+  return guard([&] {
+    if (!c || !st) fail(HOTRG_ERR_INVALID, "ctx/state is NULL");
+    HIPCHK(hipSetDevice(c->device));
+    size_t ne = (size_t)st->dx * st->dy * st->dx * st->dy;
+    if (host && cap < ne) fail(HOTRG_ERR_INVALID, "host buffer too small");
+    if (host) {
+      if (st->prec == HOTRG_FP64) {
+        HIPCHK(hipMemcpyAsync(host, st->Tn.p, ne * 8, hipMemcpyDeviceToHost, c->stream));
+      } else {
+        std::vector<float> f(ne);
+        HIPCHK(hipMemcpyAsync(f.data(), st->Tn.p, ne * 4, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        for (size_t i = 0; i < ne; ++i) host[i] = f[i];
+      }
+    }
+    double a = 0;
+    HIPCHK(hipMemcpyAsync(&a, st->acc.p, 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (dims) {
+      dims[0] = st->dx;
+      dims[1] = st->dy;
+    }
+    if (acc) *acc = a;
+    if (k) *k = st->k;
+  });
+}
+
+void hotrg_state_free(hotrg_ctx* c, hotrg_state* st) {
+  if (!c || !st) return;
+  hipSetDevice(c->device);
+  hipStreamSynchronize(c->stream);
+  Buf* bufs[] = {&st->Tn, &st->Xt, &st->Tp, &st->acc, &st->recs, &st->spec};
+  for (Buf* b : bufs) ctx_free(c, *b);
+  delete st;
+}
+
+hotrg_status hotrg_run(hotrg_ctx* c, const hotrg_model_params* params, const hotrg_opts* o,
+                       hotrg_result* res) {
+  hotrg_state* st = nullptr;
+  hotrg_status s = guard([&] {
+    if (!c || !res) fail(HOTRG_ERR_INVALID, "ctx/result is NULL");
+    check_opts(o);
+    HIPCHK(hipSetDevice(c->device));
+    auto t0 = std::chrono::steady_clock::now();
+    int dx = 0, dy = 0;
+    std::vector<double> T0 = build_tensor(params, &dx, &dy);
+    st = new_state(c, T0, dx, dy, o->prec);
+    std::vector<int> dxs, dys, dns;
+    for (int k = 0; k < o->n_steps; ++k) {
+      dxs.push_back(st->dx);
+      dys.push_back(st->dy);
+      do_step(c, st, o);
+      dns.push_back(st->dy);
+    }
+    double lnz = 0;
+    hotrg_status fs = hotrg_finish(c, st, &lnz);
+    if (fs != HOTRG_OK) fail(fs, g_err);
+    if (res->steps || res->spectra) {
+      fetch_info(c, st, 0, o->n_steps, nullptr, res->steps, res->spectra);
+      if (res->steps)
+        for (int k = 0; k < o->n_steps; ++k) {
+          res->steps[k].dx = dxs[k];
+          res->steps[k].dy = dys[k];
+          res->steps[k].d_new = dns[k];
+        }
+    }
+    res->lnz_per_site = lnz;
+    res->n_steps = o->n_steps;
+    res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  });
+  if (st) hotrg_state_free(c, st);
+  return s;
+}
+
+hotrg_status hotrg_ctx_enable_timing(hotrg_ctx* c, int on) {
+  return guard([&] {
+    if (!c) fail(HOTRG_ERR_INVALID, "ctx is NULL");
+    c->timing = on != 0;
+  });
+}
+
+int hotrg_ctx_timings(hotrg_ctx* c, hotrg_phase_time* out, int cap) {
+  int n = -1;
+  hotrg_status s = guard([&] {
+    if (!c) fail(HOTRG_ERR_INVALID, "ctx is NULL");
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    n = 0;
+    for (auto& m : c->marks) {
+      if (out && n < cap) {
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, m.a, m.b));
+        out[n++] = hotrg_phase_time{m.step, m.phase, m.dx, m.dy, m.dn, ms};
+      }
+    }
+    // events are shared between consecutive marks: return each once
+    std::vector<hipEvent_t> evs;
+    for (auto& m : c->marks) {
+      evs.push_back(m.a);
+      evs.push_back(m.b);
+    }
+    std::sort(evs.begin(), evs.end());
+    evs.erase(std::unique(evs.begin(), evs.end()), evs.end());
+    for (hipEvent_t e : evs) c->pool.push_back(e);
+    c->marks.clear();
+  });
+  return s == HOTRG_OK ? n : -1;
+}
+
+hotrg_status hotrg_environment(hotrg_ctx* c, const double* T, int dx, int dy, double* M) {
+  return guard([&] {
+    if (!c || !T || !M) fail(HOTRG_ERR_INVALID, "NULL argument");
+    if (dx < 1 || dy < 1) fail(HOTRG_ERR_INVALID, "dx, dy must be >= 1");
+    check_dims(dx, dy, 1);
+    HIPCHK(hipSetDevice(c->device));
+    const size_t ne = (size_t)dx * dy * dx * dy;
+    // Xt from T (no rotation, no scaling: maxbits = 1.0)
+    ensure(c, c->scal, 64);
+    unsigned long long one = (unsigned long long)0x3ff0000000000000ULL;
+    HIPCHK(hipMemcpyAsync(c->scal.p, &one, 8, hipMemcpyHostToDevice, c->stream));
+    ensure(c, c->Ucan, ne * 8);  // scratch for Xt
+    ensure(c, c->U1, ne * 8);    // scratch for Tn copy
+    ensure(c, c->U3, ne * 8);    // scratch for Tp
+    launch_prep(T, false, false, dx, dy, (const unsigned long long*)c->scal.p, c->U1.p, c->Ucan.p,
+                c->U3.p, false, c->stream);
+    environment_f64(c, (const double*)c->U1.p, (const double*)c->Ucan.p, dx, dy);
+    const size_t nn = (size_t)dx * dx * dx * dx;
+    HIPCHK(hipMemcpyAsync(M, c->M.p, nn * 8, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+  });
+}
+
+hotrg_status hotrg_coarse(hotrg_ctx* c, const double* T, const double* U, int dx, int dy, int dn,
+                          double* Tt, double* max_abs) {
+  return guard([&] {
+    if (!c || !T || !U || !Tt) fail(HOTRG_ERR_INVALID, "NULL argument");
+    if (dx < 1 || dy < 1 || dn < 1) fail(HOTRG_ERR_INVALID, "dims must be >= 1");
+    check_dims(dx, dy, dn);
+    HIPCHK(hipSetDevice(c->device));
+    const size_t ne = (size_t)dx * dy * dx * dy;
+    ensure(c, c->scal, 64);
+    unsigned long long one = (unsigned long long)0x3ff0000000000000ULL;
+    HIPCHK(hipMemcpyAsync(c->scal.p, &one, 8, hipMemcpyHostToDevice, c->stream));
+    ensure(c, c->A1, ne * 8);  // Tn
+    ensure(c, c->A2, ne * 8);  // Xt (unused)
+    ensure(c, c->M, ne * 8);   // Tp
+    launch_prep(T, false, false, dx, dy, (const unsigned long long*)c->scal.p, c->A1.p, c->A2.p,
+                c->M.p, false, c->stream);
+    const size_t nu = (size_t)dx * dx * dn;
+    ensure(c, c->U1, nu * 8);
+    ensure(c, c->U3, nu * 8);
+    launch_layout_u(U, dx, dn, c->U1.p, c->U3.p, false, c->stream);
+    unsigned long long* mb = (unsigned long long*)c->scal.p + 4;
+    coarse_f64(c, (const double*)c->A1.p, (const double*)c->M.p, (const double*)c->U1.p,
+               (const double*)c->U3.p, dx, dy, dn, mb);
+    const size_t no = (size_t)dn * dy * dn * dy;
+    HIPCHK(hipMemcpyAsync(Tt, c->Tt.p, no * 8, hipMemcpyDeviceToDevice, c->stream));
+    if (max_abs) HIPCHK(hipMemcpyAsync(max_abs, mb, 8, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,194 @@
+// Dense contractions of the HOTRG step as MFMA GEMMs for gfx950.
+//
+// Every contraction of a step (environment halves and combine, the three
+// coarse contractions; Sec. 2 of arXiv 2306.00358) is a plain GEMM once its
+// operands are laid out with the contracted legs contiguous; the index
+// permutation that the next contraction needs is applied in the epilogue
+// (OutMap), so no separate transpose pass touches the large intermediates.
+//
+// FP64: v_mfma_f64_16x16x4f64.  Lane layout of one 16x16x4 product
+// (64 lanes): A[i][k] from lane i + 16k, B[k][j] from lane j + 16k, and the
+// four accumulator values of lane L hold D[L/16 + 4v][L % 16], v = 0..3.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace hotrg {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ long long map_row(const OutMap& o, int m) {
+  int m2 = m % o.r2;
+  int q = m / o.r2;
+  int m1 = q % o.r1;
+  int m0 = q / o.r1;
+  return (long long)m0 * o.s0 + (long long)m1 * o.s1 + (long long)m2 * o.s2;
+}
+
+__device__ __forceinline__ long long map_col(const OutMap& o, int n) {
+  int n2 = n % o.c2;
+  int q = n / o.c2;
+  int n1 = q % o.c1;
+  int n0 = q / o.c1;
+  return (long long)n0 * o.t0 + (long long)n1 * o.t1 + (long long)n2 * o.t2;
+}
+
+__device__ __forceinline__ void atomic_max_bits(unsigned long long* p, double v) {
+  // |v| >= 0: the IEEE bit pattern of a non-negative double orders like
+  // the value; NaN patterns compare above +inf and propagate.
+  atomicMax(p, (unsigned long long)__double_as_longlong(v));
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Block tile BM x BN, K slab BK; 4 waves in a 2 x 2 arrangement, each wave
+// owns a (BM/2) x (BN/2) sub-tile made of 16x16 MFMA tiles.  Operand tiles
+// go global -> registers -> LDS; the next slab's global loads are issued
+// before the current slab's MFMAs so that they overlap.
+template <int BM, int BN, int BK, int BL>
+__global__ __launch_bounds__(256) void k_gemm_f64(const double* __restrict__ A, long long lda,
+                                                  const double* __restrict__ B, long long ldb,
+                                                  double* __restrict__ C, OutMap om, int M, int N,
+                                                  int K, unsigned long long* maxbits) {
+  constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 16, TN = WN / 16;
+  constexpr int A_PER = BM * BK / 256, B_PER = BN * BK / 256;
+  static_assert(BM * BK % 256 == 0 && BN * BK % 256 == 0, "tile must split over 256 threads");
+  __shared__ double As[BM][BK + 1];
+  // B_NCONTIG: Bs[k][n]; B_KCONTIG: Bs[n][k] (padded against bank conflicts)
+  __shared__ double Bs[BL == B_NCONTIG ? BK : BN][BL == B_NCONTIG ? BN : BK + 1];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+
+  d4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+
+  double ra[A_PER], rb[B_PER];
+
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int p = 0; p < A_PER; ++p) {
+      int e = tid + 256 * p;
+      int r = e / BK, c = e % BK;
+      int gm = m0 + r, gk = k0 + c;
+      ra[p] = (gm < M && gk < K) ? A[(long long)gm * lda + gk] : 0.0;
+    }
+#pragma unroll
+    for (int p = 0; p < B_PER; ++p) {
+      int e = tid + 256 * p;
+      if (BL == B_NCONTIG) {
+        int r = e / BN, c = e % BN;
+        int gk = k0 + r, gn = n0 + c;
+        rb[p] = (gk < K && gn < N) ? B[(long long)gk * ldb + gn] : 0.0;
+      } else {
+        int r = e / BK, c = e % BK;
+        int gn = n0 + r, gk = k0 + c;
+        rb[p] = (gk < K && gn < N) ? B[(long long)gn * ldb + gk] : 0.0;
+      }
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int p = 0; p < A_PER; ++p) {
+      int e = tid + 256 * p;
+      As[e / BK][e % BK] = ra[p];
+    }
+#pragma unroll
+    for (int p = 0; p < B_PER; ++p) {
+      int e = tid + 256 * p;
+      if (BL == B_NCONTIG)
+        Bs[e / BN][e % BN] = rb[p];
+      else
+        Bs[e / BK][e % BK] = rb[p];
+    }
+  };
+
+  const int li = lane & 15, lk = lane >> 4;
+  load(0);
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    __syncthreads();
+    store();
+    __syncthreads();
+    if (k0 + BK < K) load(k0 + BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      double a[TM], b[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) a[i] = As[wm * WM + i * 16 + li][kk + lk];
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+        b[j] = (BL == B_NCONTIG) ? Bs[kk + lk][wn * WN + j * 16 + li]
+                                 : Bs[wn * WN + j * 16 + li][kk + lk];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+  }
+
+  // epilogue: scatter through the OutMap, track max |C|
+  double mx = 0.0;
+  long long coff[TN];
+  bool cok[TN];
+#pragma unroll
+  for (int j = 0; j < TN; ++j) {
+    int n = n0 + wn * WN + j * 16 + li;
+    cok[j] = n < N;
+    coff[j] = cok[j] ? map_col(om, n) : 0;
+  }
+#pragma unroll
+  for (int i = 0; i < TM; ++i) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      int m = m0 + wm * WM + i * 16 + lk + 4 * v;
+      if (m >= M) continue;
+      long long roff = map_row(om, m);
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        if (!cok[j]) continue;
+        double x = acc[i][j][v];
+        C[roff + coff[j]] = x;
+        mx = fmax(mx, fabs(x));
+      }
+    }
+  }
+  if (maxbits) {
+    mx = wave_max(mx);
+    if (lane == 0) atomic_max_bits(maxbits, mx);
+  }
+}
+
+template <int BM, int BN, int BK>
+static void launch_f64(const double* A, long long lda, const double* B, long long ldb, int bl,
+                       double* C, const OutMap& om, int M, int N, int K,
+                       unsigned long long* maxbits, hipStream_t s) {
+  dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM);
+  if (bl == B_NCONTIG)
+    hipLaunchKernelGGL((k_gemm_f64<BM, BN, BK, B_NCONTIG>), grid, dim3(256), 0, s, A, lda, B, ldb,
+                       C, om, M, N, K, maxbits);
+  else
+    hipLaunchKernelGGL((k_gemm_f64<BM, BN, BK, B_KCONTIG>), grid, dim3(256), 0, s, A, lda, B, ldb,
+                       C, om, M, N, K, maxbits);
+}
+
+void gemm_f64(const double* A, long long lda, const double* B, long long ldb, int blayout,
+              double* C, const OutMap& om, int M, int N, int K, unsigned long long* maxbits,
+              hipStream_t s) {
+  if (M <= 0 || N <= 0) return;
+  if ((long long)M * N >= (1LL << 22) && N >= 128)
+    launch_f64<128, 128, 16>(A, lda, B, ldb, blayout, C, om, M, N, K, maxbits, s);
+  else
+    launch_f64<64, 64, 16>(A, lda, B, ldb, blayout, C, om, M, N, K, maxbits, s);
+}
+
+}  // namespace hotrg

@@ -1,0 +1,73 @@
+// Internal declarations of libhotrg: kernel launchers shared by the engine.
+// Not part of the C ABI (see include/hotrg.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hotrg {
+
+// Where a GEMM output element (m, n) is stored.  The row index is read as
+// three mixed-radix digits m = (m0 * r1 + m1) * r2 + m2 and the column as
+// n = (n0 * c1 + n1) * c2 + n2; the destination offset is
+// m0*s0 + m1*s1 + m2*s2 + n0*t0 + n1*t1 + n2*t2.  This is how the index
+// permutations between the contractions of one step are fused into the
+// GEMM epilogues instead of separate transpose passes.
+struct OutMap {
+  int r1, r2;
+  long long s0, s1, s2;
+  int c1, c2;
+  long long t0, t1, t2;
+};
+
+// Two-level map: m = mh * rr + ml -> mh*sh + ml*sl; n = nh * cr + nl -> nh*th + nl*tl.
+inline OutMap omap2(int rr, long long sh, long long sl, int cr, long long th, long long tl) {
+  OutMap o;
+  o.r1 = 1; o.r2 = rr; o.s0 = sh; o.s1 = 0; o.s2 = sl;
+  o.c1 = 1; o.c2 = cr; o.t0 = th; o.t1 = 0; o.t2 = tl;
+  return o;
+}
+
+// Plain row-major output of an M x N matrix with leading dimension ld.
+inline OutMap out_rowmajor(long long ld) { return omap2(1, ld, 0, 1, 1, 0); }
+
+enum BLayout { B_NCONTIG = 0, B_KCONTIG = 1 };
+
+// C[map(m,n)] = sum_k A[m*lda + k] * B(k, n), FP64 MFMA.
+// B(k, n) = B[k*ldb + n] for B_NCONTIG, B[n*ldb + k] for B_KCONTIG.
+// maxbits (may be null): atomic max of |C| as the bit pattern of a
+// non-negative double.
+void gemm_f64(const double* A, long long lda, const double* B, long long ldb, int blayout,
+              double* C, const OutMap& om, int M, int N, int K,
+              unsigned long long* maxbits, hipStream_t s);
+
+// Single-precision variants (FP32 MFMA; split-BF16 with three products).
+// Inputs are float; output is written as float or, when Cd is non-null,
+// as double.
+void gemm_f32(const float* A, long long lda, const float* B, long long ldb, int blayout,
+              float* C, double* Cd, const OutMap& om, int M, int N, int K,
+              unsigned long long* maxbits, bool bf16x3, hipStream_t s);
+
+// ---- small kernels (kernels.hip) ----
+void launch_maxabs(const void* x, long long n, bool is_f32, unsigned long long* maxbits, hipStream_t s);
+void launch_init_acc(const unsigned long long* maxbits, double* acc, hipStream_t s);
+// Operands of the next step from the coarse tensor `src` (f64 or f32),
+// optionally with legs transposed (l,u,r,d) -> (u,l,d,r), scaled by
+// 1/max (read from maxbits): Tn natural (dx,dy,dx,dy); Xt [(l,d),(u,r)];
+// Tp [(l,u),(d,r)].  Outputs are f64 or f32 per out_f32.
+void launch_prep(const void* src, bool src_f32, bool rotate, int dx, int dy,
+                 const unsigned long long* maxbits, void* Tn, void* Xt, void* Tp, bool out_f32,
+                 hipStream_t s);
+void launch_symmetrize(double* M, int n, hipStream_t s);
+void launch_spectrum(const double* W, int n, int dn, int trunc, double tau, int spec_len,
+                     double* spec_out, double* rec, int* kept, hipStream_t s);
+void launch_isometry(const double* V, int n, int dn, const int* kept, double* Ucan, hipStream_t s);
+void launch_layout_u(const double* Ucan, int dx, int dn, void* U1, void* U3, bool out_f32,
+                     hipStream_t s);
+void launch_norm(const unsigned long long* maxbits, const void* Tt, bool f32, int dn, int dy,
+                 double weight, double* acc, double* rec, hipStream_t s);
+void launch_finish(const void* Tn, bool f32, int dx, int dy, double weight, const double* acc,
+                   double* out, hipStream_t s);
+void launch_f64_to_f32(const double* x, float* y, long long n, hipStream_t s);
+
+}  // namespace hotrg

@@ -1,0 +1,273 @@
+// Bandwidth-bound and single-block kernels of one HOTRG step:
+// operand preparation (leg transposition, normalisation, layouts), the
+// environment symmetrisation, spectrum bookkeeping, projector extraction,
+// and the FP64 log-norm accumulation (arXiv 2306.00358, Sec. 2).
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "internal.h"
+
+namespace hotrg {
+
+static inline int nblocks(long long n, int t) {
+  long long b = (n + t - 1) / t;
+  return (int)(b < 65536 ? (b > 0 ? b : 1) : 65536);
+}
+
+__device__ __forceinline__ double ld_any(const void* p, long long i, bool f32) {
+  return f32 ? (double)((const float*)p)[i] : ((const double*)p)[i];
+}
+__device__ __forceinline__ void st_any(void* p, long long i, double v, bool f32) {
+  if (f32)
+    ((float*)p)[i] = (float)v;
+  else
+    ((double*)p)[i] = v;
+}
+
+// ---------------------------------------------------------------- max|x| --
+__global__ void k_maxabs(const void* x, long long n, bool f32, unsigned long long* maxbits) {
+  double m = 0.0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    m = fmax(m, fabs(ld_any(x, i, f32)));
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(maxbits, (unsigned long long)__double_as_longlong(m));
+}
+
+void launch_maxabs(const void* x, long long n, bool is_f32, unsigned long long* maxbits,
+                   hipStream_t s) {
+  hipLaunchKernelGGL(k_maxabs, dim3(nblocks(n, 256) < 1024 ? nblocks(n, 256) : 1024), dim3(256),
+                     0, s, x, n, is_f32, maxbits);
+}
+
+__global__ void k_init_acc(const unsigned long long* maxbits, double* acc) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) acc[0] = log(__longlong_as_double((long long)*maxbits));
+}
+
+void launch_init_acc(const unsigned long long* maxbits, double* acc, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_acc, dim3(1), dim3(64), 0, s, maxbits, acc);
+}
+
+// ------------------------------------------------------------- operands --
+// Destination tensor T[l,u,r,d] of dims (dx,dy,dx,dy).  With `rotate`, the
+// source has dims (dy,dx,dy,dx) and T[l,u,r,d] = src[u,l,d,r].
+__global__ void k_prep(const void* src, bool src_f32, bool rotate, int dx, int dy,
+                       const unsigned long long* maxbits, void* Tn, void* Xt, void* Tp,
+                       bool out_f32) {
+  const double inv = 1.0 / __longlong_as_double((long long)*maxbits);
+  const long long total = (long long)dx * dy * dx * dy;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    long long q = e;
+    int d = (int)(q % dy); q /= dy;
+    int r = (int)(q % dx); q /= dx;
+    int u = (int)(q % dy); q /= dy;
+    int l = (int)q;
+    long long si = rotate ? (((long long)u * dx + l) * dy + d) * dx + r : e;
+    double v = ld_any(src, si, src_f32) * inv;
+    st_any(Tn, e, v, out_f32);
+    // Xt[(l,d),(u,r)]
+    st_any(Xt, (((long long)l * dy + d) * dy + u) * dx + r, v, out_f32);
+    // Tp[(l,u),(d,r)]: T[a,c,e,l] read as rows (a,c), columns (l,e)
+    st_any(Tp, (((long long)l * dy + u) * dy + d) * dx + r, v, out_f32);
+  }
+}
+
+void launch_prep(const void* src, bool src_f32, bool rotate, int dx, int dy,
+                 const unsigned long long* maxbits, void* Tn, void* Xt, void* Tp, bool out_f32,
+                 hipStream_t s) {
+  long long total = (long long)dx * dy * dx * dy;
+  hipLaunchKernelGGL(k_prep, dim3(nblocks(total, 256)), dim3(256), 0, s, src, src_f32, rotate, dx,
+                     dy, maxbits, Tn, Xt, Tp, out_f32);
+}
+
+// ------------------------------------------------------------ environment --
+__global__ void k_symmetrize(double* M, int n) {
+  long long total = (long long)n * n;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    int r = (int)(e / n), c = (int)(e % n);
+    if (r < c) {
+      double a = M[(long long)r * n + c], b = M[(long long)c * n + r];
+      double v = 0.5 * (a + b);
+      M[(long long)r * n + c] = v;
+      M[(long long)c * n + r] = v;
+    }
+  }
+}
+
+void launch_symmetrize(double* M, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_symmetrize, dim3(nblocks((long long)n * n, 256)), dim3(256), 0, s, M, n);
+}
+
+// --------------------------------------------------------------- spectrum --
+// W: eigenvalues of M in ascending order.  lambda_m = W[n-1-m] (descending).
+// rec[1] = truncation error, rec[2] = cut gap, rec[4] = kept (as double).
+// Sums use a fixed-order tree so the result does not depend on scheduling.
+__global__ void k_spectrum(const double* W, int n, int dn, int trunc, double tau, int spec_len,
+                           double* spec_out, double* rec, int* kept_out) {
+  __shared__ double red[256];
+  __shared__ int kept_s;
+  const int t = threadIdx.x;
+  const double l1 = W[n - 1];
+  if (t == 0) {
+    int kept = dn;
+    if (trunc == 1 && dn < n)
+      while (kept > 0 && (W[n - kept] - W[n - 1 - kept]) <= tau * l1) --kept;
+    kept_s = kept;
+    *kept_out = kept;
+  }
+  __syncthreads();
+  const int kept = kept_s;
+  // total = trace(M), kept part
+  double tot = 0.0, kp = 0.0;
+  for (int m = t; m < n; m += 256) {
+    double lm = W[n - 1 - m];
+    tot += lm;
+    if (m < kept) kp += lm;
+  }
+  red[t] = tot;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o) red[t] += red[t + o];
+    __syncthreads();
+  }
+  tot = red[0];
+  __syncthreads();
+  red[t] = kp;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o) red[t] += red[t + o];
+    __syncthreads();
+  }
+  kp = red[0];
+  if (t == 0) {
+    rec[1] = 1.0 - kp / tot;
+    rec[2] = dn < n ? (W[n - dn] - W[n - 1 - dn]) / l1 : -1.0;
+    rec[4] = (double)kept;
+  }
+  if (spec_out)
+    for (int m = t; m < spec_len; m += 256) spec_out[m] = m < n ? W[n - 1 - m] / l1 : 0.0;
+}
+
+void launch_spectrum(const double* W, int n, int dn, int trunc, double tau, int spec_len,
+                     double* spec_out, double* rec, int* kept, hipStream_t s) {
+  hipLaunchKernelGGL(k_spectrum, dim3(1), dim3(256), 0, s, W, n, dn, trunc, tau, spec_len,
+                     spec_out, rec, kept);
+}
+
+// ------------------------------------------------------------- projector --
+// V: eigenvectors of M, column-major (column c = eigenvalue W[c], ascending).
+// Ucan[(a*dx + b)*dn + i] = U[a,b,i] = V[:, n-1-i] (zero for i >= kept).
+__global__ void k_isometry(const double* V, int n, int dn, const int* kept, double* Ucan) {
+  const int kp = *kept;
+  long long total = (long long)n * dn;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    int i = (int)(e % dn);
+    int row = (int)(e / dn);
+    Ucan[e] = i < kp ? V[(long long)(n - 1 - i) * n + row] : 0.0;
+  }
+}
+
+void launch_isometry(const double* V, int n, int dn, const int* kept, double* Ucan,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_isometry, dim3(nblocks((long long)n * dn, 256)), dim3(256), 0, s, V, n, dn,
+                     kept, Ucan);
+}
+
+// U1[(i*dx + a)*dx + b] = U[a,b,i]     (A operand of the first contraction)
+// U3[(d*dx + e)*dn + k] = U[e,d,k]     (B operand of the last contraction)
+__global__ void k_layout_u(const double* Ucan, int dx, int dn, void* U1, void* U3, bool f32) {
+  long long total = (long long)dx * dx * dn;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    int i = (int)(e % dn);
+    int ab = (int)(e / dn);
+    int a = ab / dx, b = ab % dx;
+    double v = Ucan[e];
+    st_any(U1, ((long long)i * dx + a) * dx + b, v, f32);
+    // e index of U3 is (d,e) with U[e,d,k]: here (a,b) plays (e,d)
+    st_any(U3, ((long long)b * dx + a) * dn + i, v, f32);
+  }
+}
+
+void launch_layout_u(const double* Ucan, int dx, int dn, void* U1, void* U3, bool out_f32,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_layout_u, dim3(nblocks((long long)dx * dx * dn, 256)), dim3(256), 0, s,
+                     Ucan, dx, dn, U1, U3, out_f32);
+}
+
+// ------------------------------------------------------ log-norm and trace --
+// n_k from maxbits; acc += w ln n_k; trace of the normalised coarse tensor
+// Tt (dims (dn,dy,dn,dy)) gives the torus estimate.
+// rec[0] = ln n_k, rec[3] = acc + w ln trace (NaN if trace <= 0).
+__global__ void k_norm(const unsigned long long* maxbits, const void* Tt, bool f32, int dn, int dy,
+                       double w, double* acc, double* rec) {
+  __shared__ double red[256];
+  const int t = threadIdx.x;
+  const double nk = __longlong_as_double((long long)*maxbits);
+  double s = 0.0;
+  const int cnt = dn * dy;
+  for (int e = t; e < cnt; e += 256) {
+    int i = e / dy, j = e % dy;
+    s += ld_any(Tt, (((long long)i * dy + j) * dn + i) * dy + j, f32);
+  }
+  red[t] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o) red[t] += red[t + o];
+    __syncthreads();
+  }
+  if (t == 0) {
+    double ln = log(nk);
+    double a = acc[0] + w * ln;
+    acc[0] = a;
+    double tr = red[0] / nk;
+    rec[0] = ln;
+    rec[3] = tr > 0.0 ? a + w * log(tr) : __longlong_as_double(0x7ff8000000000000LL);
+  }
+}
+
+void launch_norm(const unsigned long long* maxbits, const void* Tt, bool f32, int dn, int dy,
+                 double weight, double* acc, double* rec, hipStream_t s) {
+  hipLaunchKernelGGL(k_norm, dim3(1), dim3(256), 0, s, maxbits, Tt, f32, dn, dy, weight, acc, rec);
+}
+
+// ln Z / N = acc + w ln sum_{i,j} T[i,j,i,j]  (periodic trace, Sec. 2)
+__global__ void k_finish(const void* Tn, bool f32, int dx, int dy, double w, const double* acc,
+                         double* out) {
+  __shared__ double red[256];
+  const int t = threadIdx.x;
+  double s = 0.0;
+  const int cnt = dx * dy;
+  for (int e = t; e < cnt; e += 256) {
+    int i = e / dy, j = e % dy;
+    s += ld_any(Tn, (((long long)i * dy + j) * dx + i) * dy + j, f32);
+  }
+  red[t] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o) red[t] += red[t + o];
+    __syncthreads();
+  }
+  if (t == 0)
+    out[0] = red[0] > 0.0 ? acc[0] + w * log(red[0]) : __longlong_as_double(0x7ff8000000000000LL);
+}
+
+void launch_finish(const void* Tn, bool f32, int dx, int dy, double weight, const double* acc,
+                   double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, Tn, f32, dx, dy, weight, acc, out);
+}
+
+__global__ void k_f64_to_f32(const double* x, float* y, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    y[i] = (float)x[i];
+}
+
+void launch_f64_to_f32(const double* x, float* y, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(k_f64_to_f32, dim3(nblocks(n, 256)), dim3(256), 0, s, x, y, n);
+}
+
+}  // namespace hotrg

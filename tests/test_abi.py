@@ -1,0 +1,70 @@
+"""The C-ABI library loads and exports every function include/hotrg.h
+declares (no compute call: this runs without a GPU)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hotrg.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hotrg_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("hotrg_init_tensor", "hotrg_step", "hotrg_run", "hotrg_finish"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2306_00358_amd import _lib
+
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libhotrg.so is not built (run python -m paper_2306_00358_amd.build)")
+    L = ctypes.CDLL(_lib.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_binding_names_match_header():
+    from paper_2306_00358_amd import _lib
+
+    assert sorted(_lib.EXPORTS) == sorted(n for n in declared_functions() if n in _lib.EXPORTS)
+    assert set(_lib.EXPORTS) <= set(declared_functions())
+
+
+def test_struct_layouts_match_header():
+    # field order and sizes of the ctypes mirrors against the C declarations
+    from paper_2306_00358_amd import _lib
+
+    assert ctypes.sizeof(_lib.StepInfo) == 4 * 4 + 4 * 8
+    assert ctypes.sizeof(_lib.Opts) == 4 * 4 + 8 + 8  # 4 ints, double, int + padding
+    assert [f for f, _ in _lib.ModelParams._fields_] == [
+        "model", "beta", "J", "n_max", "q", "raw", "raw_dx", "raw_dy"]
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    from paper_2306_00358_amd import _lib
+
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "nope.so"))
+    with pytest.raises(RuntimeError, match="not built"):
+        _lib.lib()
+
+
+def test_flop_model_matches_oracle_bookkeeping():
+    from oracle import hotrg
+    from paper_2306_00358_amd import flops
+
+    for d0, dc, K in [(2, 8, 20), (2, 64, 30), (7, 24, 25)]:
+        assert flops.dims_schedule(d0, dc, K) == hotrg.dims_schedule(d0, dc, K)
+        for d in flops.dims_schedule(d0, dc, K):
+            # the oracle counts each Gram half as a full square product too
+            assert flops.step_flops(*d)["total"] == hotrg.step_flops(*d)

@@ -287,3 +287,12 @@ def test_planted_smallest_vectors_is_caught(monkeypatch):
 def test_planted_missing_rotation_is_caught(monkeypatch):
     monkeypatch.setattr(hotrg, "rotate", _rotate_missing)
     assert pin_random_torus(D=2, K=2) > 1e-6
+
+
+def test_coarse_tensor_slice_matches_full():
+    rng = np.random.default_rng(11)
+    T = rng.standard_normal((3, 4, 3, 4))
+    U = rng.standard_normal((3, 3, 5))
+    full = hotrg.coarse_tensor(T, U)
+    for i, k in [(0, 0), (2, 4), (4, 1)]:
+        assert np.abs(hotrg.coarse_tensor_slice(T, U, i, k) - full[i, :, k, :]).max() <= 1e-12
