@@ -209,15 +209,15 @@ void environment_f64(hotrg_ctx* c, const double* Tn, const double* Xt, int dx, i
   // rows (i,e): i -> dx*dy^2, e -> dy; cols (k,f): k -> dy^2, f -> 1
   const OutMap o2 = omap2(dy, dx * K2, dy, dy, K2, 1);
   gemm_f64(Tn, P, Tn, P, B_KCONTIG, (double*)c->A2.p, o2, (int)P, (int)P, (int)P, nullptr,
-           c->stream);
+           c->stream, GEMM_TAG_ENV);
   // A1[(j,e),(l,f)] = sum_{a,b} T[j,a,b,e] T[l,a,b,f] from Xt[(l,d),(u,r)], stored as A1'[(j,l),(e,f)]
   gemm_f64(Xt, P, Xt, P, B_KCONTIG, (double*)c->A1.p, o2, (int)P, (int)P, (int)P, nullptr,
-           c->stream);
+           c->stream, GEMM_TAG_ENV);
   // M[(i,j),(k,l)] = sum_{e,f} A2'[(i,k),(e,f)] A1'[(j,l),(e,f)]: GEMM rows (i,k), cols (j,l)
   // rows (i,k): i -> dx*n, k -> dx; cols (j,l): j -> n, l -> 1
   const OutMap om = omap2(dx, dx * n, dx, dx, n, 1);
   gemm_f64((const double*)c->A2.p, K2, (const double*)c->A1.p, K2, B_KCONTIG, (double*)c->M.p, om,
-           (int)n, (int)n, (int)K2, nullptr, c->stream);
+           (int)n, (int)n, (int)K2, nullptr, c->stream, GEMM_TAG_ENV);
 }
 
 // C1, C2, C3 in FP64: T~[i,j,k,l] (dims dn,dy,dn,dy) into c->Tt, max into scal.
@@ -243,7 +243,7 @@ void coarse_f64(hotrg_ctx* c, const double* Tn, const double* Tp, const double* 
   const OutMap o2 = omap2(dx, (long long)dy * n, dx, dx, n, 1);
   mark(c, HOTRG_PHASE_C2);
   gemm_f64((const double*)c->X1.p, Q, Tp, Q, B_NCONTIG, (double*)c->X2.p, o2, dn * dy * dx,
-           (int)Q, (int)Q, nullptr, c->stream);
+           (int)Q, (int)Q, nullptr, c->stream, GEMM_TAG_C2);
   // C3: rows (i,j,l) = (ij)*dy + l, cols k; K = (d,e).
   //     T~[i,j,k,l] at ((ij)*dn + k)*dy + l
   mark(c, HOTRG_PHASE_C3);
@@ -674,7 +674,13 @@ hotrg_status hotrg_environment(hotrg_ctx* c, const double* T, int dx, int dy, do
     ensure(c, c->U3, ne * 8);    // scratch for Tp
     launch_prep(T, false, false, dx, dy, (const unsigned long long*)c->scal.p, c->U1.p, c->Ucan.p,
                 c->U3.p, false, c->stream);
+    c->m_step = 0;
+    c->m_dx = dx;
+    c->m_dy = dy;
+    c->m_dn = dx * dx;
+    mark(c, HOTRG_PHASE_ENV);
     environment_f64(c, (const double*)c->U1.p, (const double*)c->Ucan.p, dx, dy);
+    mark(c, -1);
     const size_t nn = (size_t)dx * dx * dx * dx;
     HIPCHK(hipMemcpyAsync(M, c->M.p, nn * 8, hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(hipGetLastError());
@@ -703,8 +709,13 @@ hotrg_status hotrg_coarse(hotrg_ctx* c, const double* T, const double* U, int dx
     ensure(c, c->U3, nu * 8);
     launch_layout_u(U, dx, dn, c->U1.p, c->U3.p, false, c->stream);
     unsigned long long* mb = (unsigned long long*)c->scal.p + 4;
+    c->m_step = 0;
+    c->m_dx = dx;
+    c->m_dy = dy;
+    c->m_dn = dn;
     coarse_f64(c, (const double*)c->A1.p, (const double*)c->M.p, (const double*)c->U1.p,
                (const double*)c->U3.p, dx, dy, dn, mb);
+    mark(c, -1);
     const size_t no = (size_t)dn * dy * dn * dy;
     HIPCHK(hipMemcpyAsync(Tt, c->Tt.p, no * 8, hipMemcpyDeviceToDevice, c->stream));
     if (max_abs) HIPCHK(hipMemcpyAsync(max_abs, mb, 8, hipMemcpyDeviceToDevice, c->stream));

@@ -11,6 +11,8 @@
 // four accumulator values of lane L hold D[L/16 + 4v][L % 16], v = 0..3.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+
 #include "internal.h"
 
 namespace hotrg {
@@ -168,6 +170,136 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const double* __restrict__ A, 
   }
 }
 
+// Large-GEMM variant: 128 x 128 block tile, K slab BK = 32, LDS double
+// buffered so that one barrier per slab separates the MFMAs of slab s from
+// the LDS stores of slab s+1 (whose global loads were issued before the
+// MFMAs of slab s).  TAG only gives each call site its own kernel symbol,
+// so per-contraction times can be read from a kernel trace.
+template <int BL, int TAG>
+__global__ __launch_bounds__(256) void k_gemm_f64_big(const double* __restrict__ A, long long lda,
+                                                      const double* __restrict__ B, long long ldb,
+                                                      double* __restrict__ C, OutMap om, int M,
+                                                      int N, int K, unsigned long long* maxbits) {
+  constexpr int BM = 128, BN = 128, BK = 32;
+  constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 16, TN = WN / 16;
+  constexpr int A_PER = BM * BK / 256, B_PER = BN * BK / 256;
+  constexpr int AS = BK + 1;                               // A row pitch (doubles)
+  constexpr int BR = BL == B_NCONTIG ? BK : BN;            // B rows in LDS
+  constexpr int BP = BL == B_NCONTIG ? BN : BK + 1;        // B row pitch
+  __shared__ double As[2][BM * AS];
+  __shared__ double Bs[2][BR * BP];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+
+  d4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+
+  double ra[A_PER], rb[B_PER];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int p = 0; p < A_PER; ++p) {
+      int e = tid + 256 * p;
+      int r = e / BK, c = e % BK;
+      int gm = m0 + r, gk = k0 + c;
+      ra[p] = (gm < M && gk < K) ? A[(long long)gm * lda + gk] : 0.0;
+    }
+#pragma unroll
+    for (int p = 0; p < B_PER; ++p) {
+      int e = tid + 256 * p;
+      if (BL == B_NCONTIG) {
+        int r = e / BN, c = e % BN;
+        int gk = k0 + r, gn = n0 + c;
+        rb[p] = (gk < K && gn < N) ? B[(long long)gk * ldb + gn] : 0.0;
+      } else {
+        int r = e / BK, c = e % BK;
+        int gn = n0 + r, gk = k0 + c;
+        rb[p] = (gk < K && gn < N) ? B[(long long)gn * ldb + gk] : 0.0;
+      }
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int p = 0; p < A_PER; ++p) {
+      int e = tid + 256 * p;
+      As[buf][(e / BK) * AS + e % BK] = ra[p];
+    }
+#pragma unroll
+    for (int p = 0; p < B_PER; ++p) {
+      int e = tid + 256 * p;
+      if (BL == B_NCONTIG)
+        Bs[buf][(e / BN) * BP + e % BN] = rb[p];
+      else
+        Bs[buf][(e / BK) * BP + e % BK] = rb[p];
+    }
+  };
+
+  const int li = lane & 15, lk = lane >> 4;
+  const int nslab = (K + BK - 1) / BK;
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int s = 0; s < nslab; ++s) {
+    const int cur = s & 1;
+    if (s + 1 < nslab) load((s + 1) * BK);
+    const double* as = As[cur];
+    const double* bs = Bs[cur];
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      double a[TM], b[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) a[i] = as[(wm * WM + i * 16 + li) * AS + kk + lk];
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+        b[j] = (BL == B_NCONTIG) ? bs[(kk + lk) * BP + wn * WN + j * 16 + li]
+                                 : bs[(wn * WN + j * 16 + li) * BP + kk + lk];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    if (s + 1 < nslab) store(cur ^ 1);
+    __syncthreads();
+  }
+
+  double mx = 0.0;
+  long long coff[TN];
+  bool cok[TN];
+#pragma unroll
+  for (int j = 0; j < TN; ++j) {
+    int n = n0 + wn * WN + j * 16 + li;
+    cok[j] = n < N;
+    coff[j] = cok[j] ? map_col(om, n) : 0;
+  }
+#pragma unroll
+  for (int i = 0; i < TM; ++i) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      int m = m0 + wm * WM + i * 16 + lk + 4 * v;
+      if (m >= M) continue;
+      long long roff = map_row(om, m);
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        if (!cok[j]) continue;
+        double x = acc[i][j][v];
+        C[roff + coff[j]] = x;
+        mx = fmax(mx, fabs(x));
+      }
+    }
+  }
+  if (maxbits) {
+    mx = wave_max(mx);
+    if (lane == 0) atomic_max_bits(maxbits, mx);
+  }
+}
+
 template <int BM, int BN, int BK>
 static void launch_f64(const double* A, long long lda, const double* B, long long ldb, int bl,
                        double* C, const OutMap& om, int M, int N, int K,
@@ -181,14 +313,47 @@ static void launch_f64(const double* A, long long lda, const double* B, long lon
                        C, om, M, N, K, maxbits);
 }
 
+template <int TAG>
+static void launch_big(const double* A, long long lda, const double* B, long long ldb, int bl,
+                       double* C, const OutMap& om, int M, int N, int K,
+                       unsigned long long* maxbits, hipStream_t s) {
+  dim3 grid((N + 127) / 128, (M + 127) / 128);
+  if (bl == B_NCONTIG)
+    hipLaunchKernelGGL((k_gemm_f64_big<B_NCONTIG, TAG>), grid, dim3(256), 0, s, A, lda, B, ldb, C,
+                       om, M, N, K, maxbits);
+  else
+    hipLaunchKernelGGL((k_gemm_f64_big<B_KCONTIG, TAG>), grid, dim3(256), 0, s, A, lda, B, ldb, C,
+                       om, M, N, K, maxbits);
+}
+
 void gemm_f64(const double* A, long long lda, const double* B, long long ldb, int blayout,
               double* C, const OutMap& om, int M, int N, int K, unsigned long long* maxbits,
-              hipStream_t s) {
+              hipStream_t s, int tag) {
   if (M <= 0 || N <= 0) return;
-  if ((long long)M * N >= (1LL << 22) && N >= 128)
+  // kernel choice for large products: HOTRG_GEMM_VARIANT (tuning only)
+  static const int variant = [] {
+    const char* e = std::getenv("HOTRG_GEMM_VARIANT");
+    return e ? std::atoi(e) : 1;
+  }();
+  if ((long long)M * N >= (1LL << 20) && N >= 128 && variant != 2 &&
+      gemm_f64_lds(A, lda, B, ldb, blayout, C, om, M, N, K, maxbits, s, tag, variant))
+    return;
+  if ((long long)M * N >= (1LL << 22) && N >= 128 && K >= 64) {
+    switch (tag) {
+      case GEMM_TAG_C2:
+        launch_big<GEMM_TAG_C2>(A, lda, B, ldb, blayout, C, om, M, N, K, maxbits, s);
+        break;
+      case GEMM_TAG_ENV:
+        launch_big<GEMM_TAG_ENV>(A, lda, B, ldb, blayout, C, om, M, N, K, maxbits, s);
+        break;
+      default:
+        launch_big<GEMM_TAG_OTHER>(A, lda, B, ldb, blayout, C, om, M, N, K, maxbits, s);
+    }
+  } else if ((long long)M * N >= (1LL << 22) && N >= 128) {
     launch_f64<128, 128, 16>(A, lda, B, ldb, blayout, C, om, M, N, K, maxbits, s);
-  else
+  } else {
     launch_f64<64, 64, 16>(A, lda, B, ldb, blayout, C, om, M, N, K, maxbits, s);
+  }
 }
 
 }  // namespace hotrg

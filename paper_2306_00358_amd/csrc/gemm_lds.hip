@@ -1,0 +1,282 @@
+// FP64 MFMA GEMM with operands streamed straight from global memory into LDS
+// (global_load_lds_dwordx4, 16 bytes per lane), for the large contractions of
+// the HOTRG step: the O(D^7) contraction and the environment products.
+//
+//   C[map(m, n)] = sum_k A[m*lda + k] * B(k, n)
+//   B(k, n) = B[k*ldb + n] (B_NCONTIG) or B[n*ldb + k] (B_KCONTIG)
+//
+// Block: WGM x WGN waves, each owning a 64 x 64 output tile of 4 x 4
+// v_mfma_f64_16x16x4f64 tiles (accumulators stay in registers for the whole
+// K loop).  K advances in slabs of BK; two LDS stages: the slab s+1 copy is
+// in flight while slab s is multiplied.
+//
+// LDS layout.  Operand rows that are K-contiguous in global memory (A, and B
+// when K-contiguous) are stored as rows of BK doubles cut into 16-byte
+// chunks; chunk c of row r is stored at chunk position c ^ swz(r), which
+// puts the 16 rows read by one 16-lane group of an MFMA fragment into 16
+// different bank groups.  N-contiguous B is stored as plain rows of BN.
+//
+// K order inside a slab.  Lane group g = lane/16 of the MFMA takes the
+// contiguous quarter k in [g*BK/4, (g+1)*BK/4) of the slab, one k per MFMA;
+// this lets each lane read its A values with 16-byte LDS loads.  The sum
+// over k is unchanged, only its rounding order differs.
+//
+// Requirements (checked by the launcher): K % BK == 0; lda, ldb even; N even
+// for B_NCONTIG; 16-byte aligned base pointers.  Rows m >= M and columns
+// n >= N are loaded from clamped (valid) addresses and never stored.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace hotrg {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(3))) void lds_void;
+
+__device__ __forceinline__ long long lmap_row(const OutMap& o, int m) {
+  int m2 = m % o.r2;
+  int q = m / o.r2;
+  int m1 = q % o.r1;
+  int m0 = q / o.r1;
+  return (long long)m0 * o.s0 + (long long)m1 * o.s1 + (long long)m2 * o.s2;
+}
+
+__device__ __forceinline__ long long lmap_col(const OutMap& o, int n) {
+  int n2 = n % o.c2;
+  int q = n / o.c2;
+  int n1 = q % o.c1;
+  int n0 = q / o.c1;
+  return (long long)n0 * o.t0 + (long long)n1 * o.t1 + (long long)n2 * o.t2;
+}
+
+template <int BK>
+__device__ __forceinline__ int swz(int r) {
+  // rows per 256-byte LDS line: BK=32 -> 1, BK=16 -> 2
+  constexpr int L = 256 / (BK * 8);
+  constexpr int CH = BK / 2;
+  return (r / L) % CH;
+}
+
+// Copy rows [0, R) x K-slab of a K-contiguous operand into swizzled LDS.
+// One wave instruction moves 1 KB = 1024 / (BK*8) rows.
+template <int R, int BK, int NW>
+__device__ __forceinline__ void load_kcontig(const double* __restrict__ G, long long ld, int row0,
+                                             int rows_valid, int k0, char* lds, int wave,
+                                             int lane) {
+  constexpr int RPI = 1024 / (BK * 8);
+  constexpr int CH = BK / 2;
+  constexpr int INSTS = R / RPI;
+  static_assert(INSTS % NW == 0, "instructions must split over waves");
+#pragma unroll
+  for (int q = 0; q < INSTS / NW; ++q) {
+    const int inst = wave + q * NW;
+    const int r = inst * RPI + lane / CH;
+    const int c = lane % CH;
+    int gr = row0 + r;
+    gr = gr < rows_valid ? gr : rows_valid - 1;
+    const double* src = G + (long long)gr * ld + k0 + 2 * (c ^ swz<BK>(r));
+    __builtin_amdgcn_global_load_lds((const void*)src, (lds_void*)(lds + inst * 1024), 16, 0, 0);
+  }
+}
+
+// Copy a BK x BN slab of an N-contiguous operand (BN = 128: one row per instruction).
+template <int BK, int BN, int NW>
+__device__ __forceinline__ void load_ncontig(const double* __restrict__ G, long long ld, int k0,
+                                             int col0, int cols_valid, char* lds, int wave,
+                                             int lane) {
+  static_assert(BN * 8 == 1024, "one 1 KB row per instruction");
+  static_assert(BK % NW == 0, "rows must split over waves");
+#pragma unroll
+  for (int q = 0; q < BK / NW; ++q) {
+    const int r = wave + q * NW;
+    int gc = col0 + 2 * lane;
+    gc = gc < cols_valid ? gc : cols_valid - 2;
+    const double* src = G + (long long)(k0 + r) * ld + gc;
+    __builtin_amdgcn_global_load_lds((const void*)src, (lds_void*)(lds + r * 1024), 16, 0, 0);
+  }
+}
+
+template <int WGM, int WGN, int BK, int BL, int TAG>
+__global__ __launch_bounds__(64 * WGM * WGN) void k_gemm_f64_lds(
+    const double* __restrict__ A, long long lda, const double* __restrict__ B, long long ldb,
+    double* __restrict__ C, OutMap om, int M, int N, int K, unsigned long long* maxbits) {
+  constexpr int NW = WGM * WGN;
+  constexpr int BM = 64 * WGM, BN = 64 * WGN;
+  constexpr int CH = BK / 2;
+  constexpr int A_BYTES = BM * BK * 8, B_BYTES = BK * BN * 8;
+  constexpr int STAGE = A_BYTES + B_BYTES;
+  constexpr int KQ = BK / 4;  // k values per lane group per slab
+  constexpr int A_INST = BM / (1024 / (BK * 8)) / NW;
+  constexpr int B_INST = BL == B_NCONTIG ? BK / NW : BN / (1024 / (BK * 8)) / NW;
+  constexpr int LOADS = A_INST + B_INST;  // global_load_lds per wave per slab
+  static_assert(LOADS <= 63, "vmcnt range");
+  __shared__ __attribute__((aligned(16))) char smem[2 * STAGE];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave / WGN, wn = wave % WGN;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int li = lane & 15, lg = lane >> 4;
+
+  d4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+
+  auto issue = [&](int k0, int stage) {
+    char* base = smem + stage * STAGE;
+    load_kcontig<BM, BK, NW>(A, lda, m0, M, k0, base, wave, lane);
+    if (BL == B_NCONTIG)
+      load_ncontig<BK, BN, NW>(B, ldb, k0, n0, N, base + A_BYTES, wave, lane);
+    else
+      load_kcontig<BN, BK, NW>(B, ldb, n0, N, k0, base + A_BYTES, wave, lane);
+  };
+
+  const int nslab = K / BK;
+  issue(0, 0);
+  for (int s = 0; s < nslab; ++s) {
+    const int cur = s & 1;
+    if (s + 1 < nslab) {
+      issue((s + 1) * BK, cur ^ 1);
+      // this wave's copies of slab s are done; those of slab s+1 may be pending
+      asm volatile("s_waitcnt vmcnt(%0)" ::"n"(LOADS) : "memory");
+    } else {
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    }
+    // every wave's copies of slab s have landed (a plain barrier: a fenced
+    // one would also wait for the slab s+1 copies still in flight)
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");  // no LDS read moves above the barrier
+    const char* as = smem + cur * STAGE;
+    const char* bs = as + A_BYTES;
+    // A values of this lane for the slab: rows wm*64 + i*16 + li, k in [lg*KQ, lg*KQ + KQ)
+    double a[4][KQ];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = wm * 64 + i * 16 + li;
+#pragma unroll
+      for (int u = 0; u < KQ / 2; ++u) {
+        const int c = lg * (KQ / 2) + u;
+        const d2 v = *(const d2*)(as + (r * CH + (c ^ swz<BK>(r))) * 16);
+        a[i][2 * u] = v.x;
+        a[i][2 * u + 1] = v.y;
+      }
+    }
+    if (BL == B_NCONTIG) {
+#pragma unroll
+      for (int t = 0; t < KQ; ++t) {
+        const int k = lg * KQ + t;
+        double b[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) b[j] = *(const double*)(bs + (k * BN + wn * 64 + j * 16 + li) * 8);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i][t], b[j], acc[i][j], 0, 0, 0);
+      }
+    } else {
+      double b[4][KQ];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int r = wn * 64 + j * 16 + li;
+#pragma unroll
+        for (int u = 0; u < KQ / 2; ++u) {
+          const int c = lg * (KQ / 2) + u;
+          const d2 v = *(const d2*)(bs + (r * CH + (c ^ swz<BK>(r))) * 16);
+          b[j][2 * u] = v.x;
+          b[j][2 * u + 1] = v.y;
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < KQ; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i][t], b[j][t], acc[i][j], 0, 0, 0);
+    }
+    // all LDS reads of this stage have returned before any wave refills it
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");  // no copy into the stage moves above the barrier
+  }
+
+  double mx = 0.0;
+  long long coff[4];
+  bool cok[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int n = n0 + wn * 64 + j * 16 + li;
+    cok[j] = n < N;
+    coff[j] = cok[j] ? lmap_col(om, n) : 0;
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int m = m0 + wm * 64 + i * 16 + lg + 4 * v;
+      if (m >= M) continue;
+      const long long roff = lmap_row(om, m);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (!cok[j]) continue;
+        const double x = acc[i][j][v];
+        C[roff + coff[j]] = x;
+        mx = fmax(mx, fabs(x));
+      }
+    }
+  }
+  if (maxbits) {
+    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+    if (lane == 0) atomicMax(maxbits, (unsigned long long)__double_as_longlong(mx));
+  }
+}
+
+template <int WGM, int WGN, int BK, int TAG>
+static void launch_lds(const double* A, long long lda, const double* B, long long ldb, int bl,
+                       double* C, const OutMap& om, int M, int N, int K,
+                       unsigned long long* maxbits, hipStream_t s) {
+  constexpr int BM = 64 * WGM, BN = 64 * WGN;
+  dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM);
+  dim3 block(64 * WGM * WGN);
+  if (bl == B_NCONTIG)
+    hipLaunchKernelGGL((k_gemm_f64_lds<WGM, WGN, BK, B_NCONTIG, TAG>), grid, block, 0, s, A, lda, B,
+                       ldb, C, om, M, N, K, maxbits);
+  else
+    hipLaunchKernelGGL((k_gemm_f64_lds<WGM, WGN, BK, B_KCONTIG, TAG>), grid, block, 0, s, A, lda, B,
+                       ldb, C, om, M, N, K, maxbits);
+}
+
+// Returns false when the operands do not meet the requirements above.
+bool gemm_f64_lds(const double* A, long long lda, const double* B, long long ldb, int blayout,
+                  double* C, const OutMap& om, int M, int N, int K, unsigned long long* maxbits,
+                  hipStream_t s, int tag, int variant) {
+  const int BK = variant == 1 ? 16 : 32;
+  if (M < 1 || N < 2 || K < BK || K % BK != 0) return false;
+  if ((lda & 1) || (ldb & 1)) return false;
+  if (blayout == B_NCONTIG && (N & 1)) return false;
+  if (((uintptr_t)A & 15) || ((uintptr_t)B & 15)) return false;
+  if (blayout == B_KCONTIG && N < 1) return false;
+  if (variant == 1) {
+    if (tag == GEMM_TAG_C2)
+      launch_lds<4, 2, 16, GEMM_TAG_C2>(A, lda, B, ldb, blayout, C, om, M, N, K, maxbits, s);
+    else if (tag == GEMM_TAG_ENV)
+      launch_lds<4, 2, 16, GEMM_TAG_ENV>(A, lda, B, ldb, blayout, C, om, M, N, K, maxbits, s);
+    else
+      launch_lds<4, 2, 16, GEMM_TAG_OTHER>(A, lda, B, ldb, blayout, C, om, M, N, K, maxbits, s);
+  } else {
+    if (tag == GEMM_TAG_C2)
+      launch_lds<2, 2, 32, GEMM_TAG_C2>(A, lda, B, ldb, blayout, C, om, M, N, K, maxbits, s);
+    else if (tag == GEMM_TAG_ENV)
+      launch_lds<2, 2, 32, GEMM_TAG_ENV>(A, lda, B, ldb, blayout, C, om, M, N, K, maxbits, s);
+    else
+      launch_lds<2, 2, 32, GEMM_TAG_OTHER>(A, lda, B, ldb, blayout, C, om, M, N, K, maxbits, s);
+  }
+  return true;
+}
+
+}  // namespace hotrg

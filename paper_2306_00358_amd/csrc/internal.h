@@ -33,13 +33,23 @@ inline OutMap out_rowmajor(long long ld) { return omap2(1, ld, 0, 1, 1, 0); }
 
 enum BLayout { B_NCONTIG = 0, B_KCONTIG = 1 };
 
+// Call-site tags: large GEMMs get a kernel symbol per tag.
+enum GemmTag { GEMM_TAG_OTHER = 0, GEMM_TAG_ENV = 1, GEMM_TAG_C2 = 2 };
+
 // C[map(m,n)] = sum_k A[m*lda + k] * B(k, n), FP64 MFMA.
 // B(k, n) = B[k*ldb + n] for B_NCONTIG, B[n*ldb + k] for B_KCONTIG.
 // maxbits (may be null): atomic max of |C| as the bit pattern of a
 // non-negative double.
 void gemm_f64(const double* A, long long lda, const double* B, long long ldb, int blayout,
               double* C, const OutMap& om, int M, int N, int K,
-              unsigned long long* maxbits, hipStream_t s);
+              unsigned long long* maxbits, hipStream_t s, int tag = GEMM_TAG_OTHER);
+
+// Direct-to-LDS FP64 GEMM (gemm_lds.hip); returns false if the operands do
+// not meet its alignment / K-multiple requirements.  variant 0: 4 waves,
+// 128 x 128 tile, K slab 32; variant 1: 8 waves, 256 x 128 tile, K slab 16.
+bool gemm_f64_lds(const double* A, long long lda, const double* B, long long ldb, int blayout,
+                  double* C, const OutMap& om, int M, int N, int K, unsigned long long* maxbits,
+                  hipStream_t s, int tag, int variant);
 
 // Single-precision variants (FP32 MFMA; split-BF16 with three products).
 // Inputs are float; output is written as float or, when Cd is non-null,

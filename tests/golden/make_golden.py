@@ -18,6 +18,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__)
 sys.path.insert(0, ROOT)
 
 from oracle import hotrg, tensors, exact  # noqa: E402
+from tests.sensitivity import spectra_drift  # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 BETA_C = math.log(1.0 + math.sqrt(2.0)) / 2.0
@@ -44,6 +45,8 @@ def ising_run(beta, d_cut, n_steps, spec_len):
     res = hotrg.run(tensors.ising(beta), d_cut, n_steps, spec_len=spec_len)
     rec = _record(res, spec_len)
     rec.update(beta=beta, d_cut=d_cut, n_steps=n_steps, seconds=time.time() - t)
+    drift, _ = spectra_drift(tensors.ising(beta), d_cut, n_steps, spec_len, base=res)
+    rec["spectra_drift"] = drift
     return rec
 
 
@@ -82,6 +85,8 @@ def xy_batch():
         res = hotrg.run(tensors.xy(beta, n_max), d_cut, 25, trunc="multiplet",
                         tau=1e-10, spec_len=d_cut + 1)
         rec = _record(res, d_cut + 1)
+        rec["spectra_drift"], _ = spectra_drift(tensors.xy(beta, n_max), d_cut, 25, d_cut + 1,
+                                                trunc="multiplet", base=res)
         rec.update(index=i, beta=beta, n_max=n_max, d_cut=d_cut, n_steps=25,
                    trunc="multiplet", tau=1e-10, seconds=time.time() - t)
         runs.append(rec)
