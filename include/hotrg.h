@@ -64,6 +64,13 @@ typedef enum {
                                dropped whole and U is padded with zero columns */
 } hotrg_trunc;
 
+typedef enum {
+  HOTRG_EIG_AUTO = 0,  /* block subspace iteration (FP64, Rayleigh-Ritz) when
+                          D' is small against dx*dx, dense solver otherwise or
+                          if the iteration does not converge */
+  HOTRG_EIG_DENSE = 1  /* always the dense FP64 solver (rocSOLVER dsyevd) */
+} hotrg_eig;
+
 typedef struct {
   int model;          /* hotrg_model */
   double beta;        /* inverse temperature 1/T (k_B = 1) */
@@ -82,6 +89,7 @@ typedef struct {
   int trunc;          /* hotrg_trunc */
   double degen_tol;   /* multiplet tolerance tau (relative to lambda_1) */
   int spec_len;       /* spectrum values recorded per step (0: none) */
+  int eig;            /* hotrg_eig: how the leading eigenpairs of M are found */
 } hotrg_opts;
 
 typedef struct {

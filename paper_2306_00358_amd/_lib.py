@@ -43,7 +43,7 @@ class ModelParams(ctypes.Structure):
 
 class Opts(ctypes.Structure):
     _fields_ = [("d_cut", c_int), ("n_steps", c_int), ("prec", c_int), ("trunc", c_int),
-                ("degen_tol", c_double), ("spec_len", c_int)]
+                ("degen_tol", c_double), ("spec_len", c_int), ("eig", c_int)]
 
 
 class StepInfo(ctypes.Structure):
@@ -124,8 +124,13 @@ def model_params(model="ising", beta=0.44, J=1.0, n_max=0, q=2, raw=None):
     return p
 
 
-def make_opts(d_cut, n_steps=0, prec="fp64", trunc="plain", degen_tol=1e-10, spec_len=0):
+EIG = {"auto": 0, "dense": 1}
+
+
+def make_opts(d_cut, n_steps=0, prec="fp64", trunc="plain", degen_tol=1e-10, spec_len=0,
+              eig="auto"):
     o = Opts()
+    o.eig = EIG[eig] if isinstance(eig, str) else int(eig)
     o.d_cut, o.n_steps = int(d_cut), int(n_steps)
     o.prec = PREC[prec] if isinstance(prec, str) else int(prec)
     o.trunc = TRUNC[trunc] if isinstance(trunc, str) else int(trunc)

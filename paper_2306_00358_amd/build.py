@@ -18,7 +18,8 @@ LIB = os.path.join(PKG, "libhotrg.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.path.join(ROCM, "bin", "hipcc")
 
-SOURCES = ["engine.hip", "gemm.hip", "gemm_lds.hip", "gemm_f32.hip", "kernels.hip", "models.cpp"]
+SOURCES = ["engine.hip", "eigs.hip", "gemm.hip", "gemm_lds.hip", "gemm_f32.hip", "kernels.hip",
+           "models.cpp"]
 
 CFLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -64,8 +64,11 @@ struct hotrg_ctx {
   size_t in_use = 0;
   rocblas_handle blas = nullptr;
   // step workspace, grown on demand
-  Buf A1, A2, M, W, E, Ucan, U1, U3, X1, X2, Tt, scal;
-  // scal layout: [0] maxbits (u64), [1] info (int), [2] kept (int), [3] finish out (double)
+  Buf A1, A2, M, W, E, Ucan, U1, U3, X1, X2, Tt, scal, EW, Xr;
+  // scal layout (bytes): 0 maxbits (u64), 8 info (int), 16 kept (int), 24 finish out (double),
+  // 32 primitive max (u64), 40 trace(M) (double), 48 iterative solver info (int)
+  int last_eig_iters = 0;      // sweeps of the last iterative solve (0: dense solver)
+  double last_eig_resid = 0.0;
   // per-phase timing
   bool timing = false;
   struct Mark {
@@ -183,6 +186,8 @@ void check_opts(const hotrg_opts* o) {
   if (o->trunc == HOTRG_TRUNC_MULTIPLET && !(o->degen_tol >= 0.0))
     fail(HOTRG_ERR_INVALID, "degen_tol must be >= 0");
   if (o->spec_len < 0) fail(HOTRG_ERR_INVALID, "spec_len must be >= 0");
+  if (o->eig != HOTRG_EIG_AUTO && o->eig != HOTRG_EIG_DENSE)
+    fail(HOTRG_ERR_INVALID, "eig must be HOTRG_EIG_AUTO or HOTRG_EIG_DENSE");
   check_prec(o->prec);
 }
 
@@ -326,18 +331,47 @@ void do_step(hotrg_ctx* c, hotrg_state* st, const hotrg_opts* o) {
   // a3: FP64 eigendecomposition, spectrum and projector
   ensure(c, c->W, (size_t)n * 8);
   ensure(c, c->E, (size_t)n * 8);
+  double* trace = (double*)((char*)c->scal.p + 40);
+  launch_trace((const double*)c->M.p, n, trace, c->stream);
   mark(c, HOTRG_PHASE_EIGH);
-  rocblas_status rs = rocsolver_dsyevd(c->blas, rocblas_evect_original, rocblas_fill_lower, n,
-                                       (double*)c->M.p, n, (double*)c->W.p, (double*)c->E.p, info);
-  if (rs != rocblas_status_success)
-    fail(HOTRG_ERR_DEVICE, "rocsolver_dsyevd failed with status " + std::to_string((int)rs));
+  // leading eigenpairs: block subspace iteration when D' is small against n
+  const int need = std::max(dn + 1, std::min(o->spec_len, n));
+  int p = std::min(128, std::max(2 * dn, need + 16));
+  p = (p + 15) / 16 * 16;
+  bool sub = o->eig == HOTRG_EIG_AUTO && n >= 1024 && need + 16 <= p && p <= 128 && p * 4 <= n;
+  const double* evec = nullptr;
+  int cols = n;
+  if (sub) {
+    ensure(c, c->EW, topk_workspace_doubles(n, p) * 8);
+    ensure(c, c->Xr, (size_t)p * n * 8);
+    int iters = 0;
+    double resid = 0.0;
+    sub = topk_eigs(c->blas, (const double*)c->M.p, n, p, need, 5e-14, (double*)c->EW.p,
+                    (double*)c->W.p, (double*)c->Xr.p, (int*)((char*)c->scal.p + 48), &iters,
+                    &resid, c->stream);
+    c->last_eig_iters = sub ? iters : 0;
+    c->last_eig_resid = resid;
+    if (sub) {
+      evec = (const double*)c->Xr.p;
+      cols = p;
+    }
+  }
+  if (!sub) {
+    rocblas_status rs = rocsolver_dsyevd(c->blas, rocblas_evect_original, rocblas_fill_lower, n,
+                                         (double*)c->M.p, n, (double*)c->W.p, (double*)c->E.p,
+                                         info);
+    if (rs != rocblas_status_success)
+      fail(HOTRG_ERR_DEVICE, "rocsolver_dsyevd failed with status " + std::to_string((int)rs));
+    evec = (const double*)c->M.p;
+    cols = n;
+  }
   mark(c, HOTRG_PHASE_PROJ);
-  launch_spectrum((const double*)c->W.p, n, dn, o->trunc, o->degen_tol, st->spec_len, spec, rec,
-                  kept, c->stream);
+  launch_spectrum((const double*)c->W.p, cols, n, dn, o->trunc, o->degen_tol, st->spec_len,
+                  trace, spec, rec, kept, c->stream);
   ensure(c, c->Ucan, (size_t)n * dn * 8);
   ensure(c, c->U1, (size_t)n * dn * 8);
   ensure(c, c->U3, (size_t)n * dn * 8);
-  launch_isometry((const double*)c->M.p, n, dn, kept, (double*)c->Ucan.p, c->stream);
+  launch_isometry(evec, cols, n, dn, kept, (double*)c->Ucan.p, c->stream);
   launch_layout_u((const double*)c->Ucan.p, dx, dn, c->U1.p, c->U3.p, false, c->stream);
   // a4..a6: the three contractions, max|T~|
   coarse_f64(c, (const double*)st->Tn.p, (const double*)st->Tp.p, (const double*)c->U1.p,
@@ -474,7 +508,7 @@ void hotrg_ctx_destroy(hotrg_ctx* c) {
   hipSetDevice(c->device);
   hipStreamSynchronize(c->stream);
   Buf* bufs[] = {&c->A1, &c->A2, &c->M, &c->W, &c->E, &c->Ucan, &c->U1, &c->U3,
-                 &c->X1, &c->X2, &c->Tt, &c->scal};
+                 &c->X1, &c->X2, &c->Tt, &c->scal, &c->EW, &c->Xr};
   for (Buf* b : bufs) ctx_free(c, *b);
   for (auto& m : c->marks) {
     c->pool.push_back(m.a);

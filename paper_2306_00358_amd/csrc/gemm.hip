@@ -54,8 +54,18 @@ template <int BM, int BN, int BK, int BL>
 __global__ __launch_bounds__(256) void k_gemm_f64(const double* __restrict__ A, long long lda,
                                                   const double* __restrict__ B, long long ldb,
                                                   double* __restrict__ C, OutMap om, int M, int N,
-                                                  int K, unsigned long long* maxbits) {
+                                                  int K, unsigned long long* maxbits, int kchunk,
+                                                  long long cstride) {
   constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 16, TN = WN / 16;
+  // split-K: block z sums k in [z*kchunk, min((z+1)*kchunk, K)) into C + z*cstride
+  if (kchunk > 0) {
+    const int z = blockIdx.z;
+    const int kb = z * kchunk;
+    A += kb;
+    B += BL == B_NCONTIG ? (long long)kb * ldb : kb;
+    C += z * cstride;
+    K = K - kb < kchunk ? K - kb : kchunk;
+  }
   constexpr int A_PER = BM * BK / 256, B_PER = BN * BK / 256;
   static_assert(BM * BK % 256 == 0 && BN * BK % 256 == 0, "tile must split over 256 threads");
   __shared__ double As[BM][BK + 1];
@@ -303,14 +313,41 @@ __global__ __launch_bounds__(256) void k_gemm_f64_big(const double* __restrict__
 template <int BM, int BN, int BK>
 static void launch_f64(const double* A, long long lda, const double* B, long long ldb, int bl,
                        double* C, const OutMap& om, int M, int N, int K,
-                       unsigned long long* maxbits, hipStream_t s) {
-  dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM);
+                       unsigned long long* maxbits, hipStream_t s, int kchunk = 0,
+                       long long cstride = 0) {
+  const int nz = kchunk > 0 ? (K + kchunk - 1) / kchunk : 1;
+  dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, nz);
   if (bl == B_NCONTIG)
     hipLaunchKernelGGL((k_gemm_f64<BM, BN, BK, B_NCONTIG>), grid, dim3(256), 0, s, A, lda, B, ldb,
-                       C, om, M, N, K, maxbits);
+                       C, om, M, N, K, maxbits, kchunk, cstride);
   else
     hipLaunchKernelGGL((k_gemm_f64<BM, BN, BK, B_KCONTIG>), grid, dim3(256), 0, s, A, lda, B, ldb,
-                       C, om, M, N, K, maxbits);
+                       C, om, M, N, K, maxbits, kchunk, cstride);
+}
+
+__global__ void k_sum_partials(const double* __restrict__ P, int parts, long long count,
+                               long long stride, double* __restrict__ out) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < count;
+       e += (long long)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int z = 0; z < parts; ++z) s += P[z * stride + e];
+    out[e] = s;
+  }
+}
+
+void gemm_f64_splitk(const double* A, long long lda, const double* B, long long ldb, int blayout,
+                     double* C, long long ldc, int M, int N, int K, int kchunk, double* partials,
+                     hipStream_t s) {
+  if (M <= 0 || N <= 0) return;
+  const int parts = (K + kchunk - 1) / kchunk;
+  const long long cstride = (long long)M * N;
+  launch_f64<64, 64, 16>(A, lda, B, ldb, blayout, partials, out_rowmajor(N), M, N, K, nullptr, s,
+                         kchunk, cstride);
+  long long count = (long long)M * N;
+  int blocks = (int)((count + 255) / 256);
+  hipLaunchKernelGGL(k_sum_partials, dim3(blocks < 4096 ? blocks : 4096), dim3(256), 0, s,
+                     partials, parts, count, cstride, C);
+  (void)ldc;
 }
 
 template <int TAG>

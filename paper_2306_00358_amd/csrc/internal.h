@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
 #include <stdint.h>
 
 namespace hotrg {
@@ -44,6 +45,13 @@ void gemm_f64(const double* A, long long lda, const double* B, long long ldb, in
               double* C, const OutMap& om, int M, int N, int K,
               unsigned long long* maxbits, hipStream_t s, int tag = GEMM_TAG_OTHER);
 
+// Split-K FP64 GEMM for products with small M x N and long K: partial
+// products of K chunks go to `partials` (ceil(K/kchunk) * M * N doubles) and
+// are summed in a fixed order into the row-major M x N matrix C.
+void gemm_f64_splitk(const double* A, long long lda, const double* B, long long ldb, int blayout,
+                     double* C, long long ldc, int M, int N, int K, int kchunk, double* partials,
+                     hipStream_t s);
+
 // Direct-to-LDS FP64 GEMM (gemm_lds.hip); returns false if the operands do
 // not meet its alignment / K-multiple requirements.  variant 0: 4 waves,
 // 128 x 128 tile, K slab 32; variant 1: 8 waves, 256 x 128 tile, K slab 16.
@@ -69,9 +77,18 @@ void launch_prep(const void* src, bool src_f32, bool rotate, int dx, int dy,
                  const unsigned long long* maxbits, void* Tn, void* Xt, void* Tp, bool out_f32,
                  hipStream_t s);
 void launch_symmetrize(double* M, int n, hipStream_t s);
-void launch_spectrum(const double* W, int n, int dn, int trunc, double tau, int spec_len,
-                     double* spec_out, double* rec, int* kept, hipStream_t s);
-void launch_isometry(const double* V, int n, int dn, const int* kept, double* Ucan, hipStream_t s);
+// W: the `cnt` leading eigenvalues of M in ascending order (cnt <= n);
+// total: trace(M) (device scalar).
+void launch_spectrum(const double* W, int cnt, int n, int dn, int trunc, double tau, int spec_len,
+                     const double* total, double* spec_out, double* rec, int* kept, hipStream_t s);
+// V: `cols` eigenvectors of length n, vector c at V[c*n], ascending order.
+void launch_isometry(const double* V, int cols, int n, int dn, const int* kept, double* Ucan,
+                     hipStream_t s);
+void launch_trace(const double* M, int n, double* out, hipStream_t s);
+size_t topk_workspace_doubles(int n, int p);
+bool topk_eigs(rocblas_handle blas, const double* M, int n, int p, int need, double tol,
+               double* ws, double* W, double* Xout, int* dinfo, int* iters, double* resid,
+               hipStream_t s);
 void launch_layout_u(const double* Ucan, int dx, int dn, void* U1, void* U3, bool out_f32,
                      hipStream_t s);
 void launch_norm(const unsigned long long* maxbits, const void* Tt, bool f32, int dn, int dy,

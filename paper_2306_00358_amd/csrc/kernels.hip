@@ -101,79 +101,69 @@ void launch_symmetrize(double* M, int n, hipStream_t s) {
 }
 
 // --------------------------------------------------------------- spectrum --
-// W: eigenvalues of M in ascending order.  lambda_m = W[n-1-m] (descending).
-// rec[1] = truncation error, rec[2] = cut gap, rec[4] = kept (as double).
-// Sums use a fixed-order tree so the result does not depend on scheduling.
-__global__ void k_spectrum(const double* W, int n, int dn, int trunc, double tau, int spec_len,
-                           double* spec_out, double* rec, int* kept_out) {
+// W: the cnt leading eigenvalues of M, ascending; lambda_m = W[cnt-1-m]
+// (descending).  total = trace(M).  rec[1] = truncation error, rec[2] = cut
+// gap, rec[4] = kept (as double).  Sums use a fixed-order tree.
+__global__ void k_spectrum(const double* W, int cnt, int n, int dn, int trunc, double tau,
+                           int spec_len, const double* total, double* spec_out, double* rec,
+                           int* kept_out) {
   __shared__ double red[256];
   __shared__ int kept_s;
   const int t = threadIdx.x;
-  const double l1 = W[n - 1];
+  const double l1 = W[cnt - 1];
   if (t == 0) {
     int kept = dn;
     if (trunc == 1 && dn < n)
-      while (kept > 0 && (W[n - kept] - W[n - 1 - kept]) <= tau * l1) --kept;
+      while (kept > 0 && (W[cnt - kept] - W[cnt - 1 - kept]) <= tau * l1) --kept;
     kept_s = kept;
     *kept_out = kept;
   }
   __syncthreads();
   const int kept = kept_s;
-  // total = trace(M), kept part
-  double tot = 0.0, kp = 0.0;
-  for (int m = t; m < n; m += 256) {
-    double lm = W[n - 1 - m];
-    tot += lm;
-    if (m < kept) kp += lm;
-  }
-  red[t] = tot;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (t < o) red[t] += red[t + o];
-    __syncthreads();
-  }
-  tot = red[0];
-  __syncthreads();
+  double kp = 0.0;
+  for (int m = t; m < kept; m += 256) kp += W[cnt - 1 - m];
   red[t] = kp;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
     if (t < o) red[t] += red[t + o];
     __syncthreads();
   }
-  kp = red[0];
   if (t == 0) {
-    rec[1] = 1.0 - kp / tot;
-    rec[2] = dn < n ? (W[n - dn] - W[n - 1 - dn]) / l1 : -1.0;
+    rec[1] = 1.0 - red[0] / total[0];
+    rec[2] = dn < n ? (W[cnt - dn] - W[cnt - 1 - dn]) / l1 : -1.0;
     rec[4] = (double)kept;
   }
   if (spec_out)
-    for (int m = t; m < spec_len; m += 256) spec_out[m] = m < n ? W[n - 1 - m] / l1 : 0.0;
+    for (int m = t; m < spec_len; m += 256) spec_out[m] = m < cnt ? W[cnt - 1 - m] / l1 : 0.0;
 }
 
-void launch_spectrum(const double* W, int n, int dn, int trunc, double tau, int spec_len,
-                     double* spec_out, double* rec, int* kept, hipStream_t s) {
-  hipLaunchKernelGGL(k_spectrum, dim3(1), dim3(256), 0, s, W, n, dn, trunc, tau, spec_len,
-                     spec_out, rec, kept);
+void launch_spectrum(const double* W, int cnt, int n, int dn, int trunc, double tau, int spec_len,
+                     const double* total, double* spec_out, double* rec, int* kept,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_spectrum, dim3(1), dim3(256), 0, s, W, cnt, n, dn, trunc, tau, spec_len,
+                     total, spec_out, rec, kept);
 }
 
 // ------------------------------------------------------------- projector --
-// V: eigenvectors of M, column-major (column c = eigenvalue W[c], ascending).
-// Ucan[(a*dx + b)*dn + i] = U[a,b,i] = V[:, n-1-i] (zero for i >= kept).
-__global__ void k_isometry(const double* V, int n, int dn, const int* kept, double* Ucan) {
+// V: `cols` eigenvectors of M of length n, vector c at V[c*n .. c*n + n),
+// ascending eigenvalue order.
+// Ucan[(a*dx + b)*dn + i] = U[a,b,i] = vector cols-1-i (zero for i >= kept).
+__global__ void k_isometry(const double* V, int cols, int n, int dn, const int* kept,
+                           double* Ucan) {
   const int kp = *kept;
   long long total = (long long)n * dn;
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
        e += (long long)gridDim.x * blockDim.x) {
     int i = (int)(e % dn);
     int row = (int)(e / dn);
-    Ucan[e] = i < kp ? V[(long long)(n - 1 - i) * n + row] : 0.0;
+    Ucan[e] = i < kp ? V[(long long)(cols - 1 - i) * n + row] : 0.0;
   }
 }
 
-void launch_isometry(const double* V, int n, int dn, const int* kept, double* Ucan,
+void launch_isometry(const double* V, int cols, int n, int dn, const int* kept, double* Ucan,
                      hipStream_t s) {
-  hipLaunchKernelGGL(k_isometry, dim3(nblocks((long long)n * dn, 256)), dim3(256), 0, s, V, n, dn,
-                     kept, Ucan);
+  hipLaunchKernelGGL(k_isometry, dim3(nblocks((long long)n * dn, 256)), dim3(256), 0, s, V, cols,
+                     n, dn, kept, Ucan);
 }
 
 // U1[(i*dx + a)*dx + b] = U[a,b,i]     (A operand of the first contraction)

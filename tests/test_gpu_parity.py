@@ -179,6 +179,17 @@ def test_run_ising_dcut32_vs_stored_oracle(ctx, idx):
     _compare_run(got, rec["lnz_per_site"], rec["steps"], rec["spectra"], drift=rec["spectra_drift"])
 
 
+def test_run_ising_dcut32_dense_eigensolver(ctx):
+    # the dense FP64 solver (rocSOLVER) path against the same stored oracle
+    from paper_2306_00358_amd import hotrg_run, make_opts, model_params
+
+    with open(os.path.join(GOLDEN, "ising_d32.json")) as f:
+        rec = json.load(f)["runs"][1]
+    got = hotrg_run(ctx, model_params("ising", beta=rec["beta"]),
+                    make_opts(32, 30, spec_len=33, eig="dense"))
+    _compare_run(got, rec["lnz_per_site"], rec["steps"], rec["spectra"], drift=rec["spectra_drift"])
+
+
 def test_run_ising_dcut64_vs_stored_oracle_and_paper(ctx):
     path = os.path.join(GOLDEN, "ising_d64.json")
     if not os.path.exists(path):
