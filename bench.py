@@ -30,6 +30,11 @@ BETA_C = math.log(1.0 + math.sqrt(2.0)) / 2.0
 ONSAGER_TC = math.log(2.0) / 2.0 + 2.0 * 0.915965594177219015054603514932384110774 / math.pi
 PEAKS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}  # TFLOP/s, dense MFMA, MI355X
 DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}
+# HBM bytes of one dominant-kernel launch at the steady-state shape, from the
+# FETCH_SIZE / WRITE_SIZE counter runs of `bench.py --kernel-probe` (scaled by
+# the readings of a 1 GiB copy); the summary and commands are under profiles/.
+# An entry is valid only for the kernel version it was measured on.
+TRAFFIC = {("fp64", 64): 9.468e10}
 
 
 def parse():
@@ -41,7 +46,34 @@ def parse():
     ap.add_argument("--d-cut", type=int, default=64)
     ap.add_argument("--n-steps", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-probe", action="store_true",
+                    help="run one coarse contraction at the benchmark shape and a 1 GiB "
+                         "calibration copy (for hardware-counter runs), then exit")
     return ap.parse_args()
+
+
+def kernel_probe(args):
+    """One launch of each coarse contraction at D = d_cut (the shape of a
+    steady-state benchmark step) on seeded inputs, preceded by a device copy
+    of exactly 1 GiB whose counter readings calibrate FETCH_SIZE/WRITE_SIZE."""
+    import torch
+
+    from paper_2306_00358_amd import Context, hotrg_coarse
+
+    D = args.d_cut
+    n = 1 << 27  # 2^27 doubles = 1 GiB
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    g = torch.Generator(device="cuda").manual_seed(0)
+    T = torch.rand((D, D, D, D), dtype=torch.float64, device="cuda", generator=g)
+    U = torch.rand((D, D, D), dtype=torch.float64, device="cuda", generator=g)
+    Tt = torch.empty_like(T)
+    with Context(0) as ctx:
+        hotrg_coarse(ctx, T, U, Tt)
+    torch.cuda.synchronize()
+    print(json.dumps({"kernel_probe": {"d": D, "copy_bytes": 8 * n}}), flush=True)
 
 
 def cpu_baseline(d_cut):
@@ -92,6 +124,9 @@ def main():
     from paper_2306_00358_amd.flops import dims_schedule, step_flops
 
     assert torch.cuda.is_available(), "no GPU"
+    if args.kernel_probe:
+        kernel_probe(args)
+        return
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     ctx = Context(0)
@@ -146,7 +181,7 @@ def main():
         "rel_err_vs_onsager": abs(lnz - ONSAGER_TC) / ONSAGER_TC,
         "phase_ms_per_run": phase_ms,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak, "traffic": TRAFFIC.get((args.prec, args.d_cut)),
                      "kernel": "C2 GEMM %dx%dx%d" % (args.d_cut**3, args.d_cut**2, args.d_cut**2),
                      "kernel_ms": c2_ms, "launches": len(c2)},
     }

@@ -44,72 +44,77 @@ __global__ void k_seed_block(double* V, long long count, unsigned long long seed
 }
 
 // G (p x p, row-major) -> RinvT = (R^-1)^T where G + s I = R^T R, s =
-// shift_rel * trace(G).  One workgroup; G lives in LDS (p <= 128).
-// R fills the upper triangle, (R^-1)^T the strict lower triangle, the
-// diagonal of R^-1 a separate array.  *fail is set if a pivot is not positive.
+// shift_rel * trace(G).  One workgroup of 1024 threads (32 x 32); G lives
+// in LDS (p <= 128).  Right-looking Cholesky: column j updates the trailing
+// upper triangle with the unscaled row j divided by its pivot, while row j
+// of R is written, scaled, into the strict lower triangle (as R^T) and the
+// pivots into rdiag -- one barrier per column.  Then Gauss-Jordan on the
+// upper triangle: X = R^-1 from X = I eliminating columns p-1 .. 0, again
+// one barrier per column (row k is scaled one column later, when nothing
+// reads it any more).  *fail is set if a pivot is not positive.
 __global__ __launch_bounds__(1024) void k_chol_inv(const double* __restrict__ G, int p,
                                                    double shift_rel, double* __restrict__ RinvT,
                                                    int* fail) {
-  extern __shared__ double A[];  // p * p, then p for the inverse diagonal, then 1024 scratch
-  double* dinv = A + p * p;
-  double* red = dinv + p;
-  const int t = threadIdx.x, nt = blockDim.x;
+  extern __shared__ double A[];  // p * p, then rdiag (p), then 1024 scratch
+  double* rdiag = A + p * p;
+  double* red = rdiag + p;
+  const int t = threadIdx.x;
+  const int tx = t & 31, ty = t >> 5;
   double tr = 0.0;
-  for (int e = t; e < p * p; e += nt) {
-    const int i = e / p, j = e % p;
-    const double v = i <= j ? G[i * p + j] : G[j * p + i];  // upper part, mirrored
-    A[e] = v;
-    if (i == j) tr += v;
-  }
+  for (int i = ty; i < p; i += 32)
+    for (int j = tx; j < p; j += 32) {
+      const double v = i <= j ? G[i * p + j] : G[j * p + i];  // upper part, mirrored
+      A[i * p + j] = v;
+      if (i == j) tr += v;
+    }
   red[t] = tr;
   __syncthreads();
-  for (int o = nt / 2; o > 0; o >>= 1) {
+  for (int o = 512; o > 0; o >>= 1) {
     if (t < o) red[t] += red[t + o];
     __syncthreads();
   }
   const double shift = shift_rel * red[0];
-  for (int i = t; i < p; i += nt) A[i * p + i] += shift;
+  if (t < p) A[t * p + t] += shift;
   __syncthreads();
-  // right-looking Cholesky, upper: A = R^T R
   for (int j = 0; j < p; ++j) {
-    if (t == 0) {
-      const double d = A[j * p + j];
-      if (!(d > 0.0)) *fail = 1;
-      A[j * p + j] = d > 0.0 ? sqrt(d) : 1.0;
+    const double d = A[j * p + j];
+    if (!(d > 0.0)) {
+      if (t == 0) *fail = 1;
+      return;  // uniform: every thread reads the same pivot
     }
-    __syncthreads();
-    const double rjj = A[j * p + j];
-    for (int k = j + 1 + t; k < p; k += nt) A[j * p + k] /= rjj;
-    __syncthreads();
-    const int w = p - j - 1;  // trailing upper triangle rows/cols j+1..p-1
-    for (int e = t; e < w * w; e += nt) {
-      const int i = j + 1 + e / w, k = j + 1 + e % w;
-      if (k >= i) A[i * p + k] -= A[j * p + i] * A[j * p + k];
+    const double rd = sqrt(d), inv_d = 1.0 / d, inv_rd = 1.0 / rd;
+    // R^T column j (lower triangle) and the pivot
+    if (ty == 0) {
+      for (int k = j + 1 + tx; k < p; k += 32) A[k * p + j] = A[j * p + k] * inv_rd;
+      if (tx == 0) rdiag[j] = rd;
     }
-    __syncthreads();
-  }
-  // X = R^-1 (upper), row by row from the bottom; X[i][j] stored at A[j][i] (j > i)
-  for (int i = p - 1; i >= 0; --i) {
-    const double rii = A[i * p + i];
-    for (int j = i + t; j < p; j += nt) {
-      if (j == i) {
-        dinv[i] = 1.0 / rii;
-      } else {
-        double s = 0.0;
-        for (int k = i + 1; k <= j; ++k) {
-          const double xkj = k == j ? dinv[j] : A[j * p + k];
-          s += A[i * p + k] * xkj;
-        }
-        A[j * p + i] = -s / rii;
-      }
+    // trailing update of the upper triangle, rows/cols j+1 .. p-1
+    for (int i = j + 1 + ty; i < p; i += 32) {
+      const double aji = A[j * p + i] * inv_d;
+      for (int k = i + tx; k < p; k += 32) A[i * p + k] -= aji * A[j * p + k];
     }
     __syncthreads();
   }
-  // RinvT[i][k] = X[k][i]: lower triangle
-  for (int e = t; e < p * p; e += nt) {
-    const int i = e / p, k = e % p;
-    RinvT[e] = k < i ? A[i * p + k] : (k == i ? dinv[i] : 0.0);
+  // X = R^-1 in the upper triangle; R[i][k] = A[k*p + i] for i < k
+  for (int i = ty; i < p; i += 32)
+    for (int c = i + tx; c < p; c += 32) A[i * p + c] = i == c ? 1.0 : 0.0;
+  __syncthreads();
+  for (int k = p - 1; k >= 0; --k) {
+    const double inv_rkk = 1.0 / rdiag[k];
+    if (k + 1 < p && ty == 31)  // scale row k+1 (final since the last column)
+      for (int c = k + 1 + tx; c < p; c += 32) A[(k + 1) * p + c] /= rdiag[k + 1];
+    for (int i = ty; i < k; i += 32) {
+      const double f = A[k * p + i] * inv_rkk;  // R[i][k] / R[k][k]
+      for (int c = k + tx; c < p; c += 32) A[i * p + c] -= f * A[k * p + c];
+    }
+    __syncthreads();
   }
+  if (ty == 0)
+    for (int c = tx; c < p; c += 32) A[c] /= rdiag[0];
+  __syncthreads();
+  // RinvT[i][k] = X[k][i] (lower triangular)
+  for (int i = ty; i < p; i += 32)
+    for (int k = tx; k < p; k += 32) RinvT[i * p + k] = k <= i ? A[k * p + i] : 0.0;
 }
 
 __global__ void k_symmetrize_small(double* H, int p) {
