@@ -124,13 +124,13 @@ void hotrg_ctx_destroy(hotrg_ctx* ctx);
 const char* hotrg_last_error(void);
 size_t hotrg_ctx_bytes_in_use(const hotrg_ctx* ctx);
 
-/* a0: build the initial tensor of `params` in FP64 on the host, upload it
+/* Build the initial tensor of `params` in FP64 on the host, upload it
  * and divide it by n_0 = max|T0| (Sec. 3: Ising, XY, Potts tensors).  The
  * state records ln n_0 and is owned by ctx until hotrg_state_free. */
 hotrg_status hotrg_init_tensor(hotrg_ctx* ctx, const hotrg_model_params* params,
                                int prec, hotrg_state** out);
 
-/* a1..a7: one directional coarse-graining step (Sec. 2, Fig. 1): environment
+/* One directional coarse-graining step (Sec. 2, Fig. 1): environment
  * M, FP64 eigendecomposition, projector U, the three contractions, the
  * transposition of legs and the normalisation.  `info` (may be NULL)
  * receives the step record and `spectrum` (host, may be NULL) the first
@@ -139,7 +139,7 @@ hotrg_status hotrg_init_tensor(hotrg_ctx* ctx, const hotrg_model_params* params,
 hotrg_status hotrg_step(hotrg_ctx* ctx, hotrg_state* st, const hotrg_opts* opts,
                         hotrg_step_info* info, double* spectrum);
 
-/* a8: ln Z / N from the steps done so far and the periodic trace. */
+/* ln Z / N from the steps done so far and the periodic trace. */
 hotrg_status hotrg_finish(hotrg_ctx* ctx, hotrg_state* st, double* lnz_per_site);
 
 /* Copy the current (normalised) tensor to the host.  `dims` receives
@@ -149,7 +149,7 @@ hotrg_status hotrg_state_export(hotrg_ctx* ctx, const hotrg_state* st, double* h
                                 int dims[2], double* acc, int* k);
 void hotrg_state_free(hotrg_ctx* ctx, hotrg_state* st);
 
-/* a0..a8: init, opts->n_steps directional steps, finish; one host wait at the
+/* Init, opts->n_steps directional steps, finish; one host wait at the
  * end.  result->steps / result->spectra are filled when non-NULL. */
 hotrg_status hotrg_run(hotrg_ctx* ctx, const hotrg_model_params* params, const hotrg_opts* opts,
                        hotrg_result* result);
@@ -160,13 +160,13 @@ hotrg_status hotrg_run(hotrg_ctx* ctx, const hotrg_model_params* params, const h
  * `out` (host) and clears the list.  It returns the number of records
  * copied, or -1 on error. */
 enum {
-  HOTRG_PHASE_ENV = 0,   /* a1+a2: environment halves, combine, symmetrise */
-  HOTRG_PHASE_EIGH = 1,  /* a3: FP64 eigendecomposition of M */
-  HOTRG_PHASE_PROJ = 2,  /* a3: spectrum, truncation, projector layouts */
-  HOTRG_PHASE_C1 = 3,    /* a4 */
-  HOTRG_PHASE_C2 = 4,    /* a5: the O(D^7) contraction */
-  HOTRG_PHASE_C3 = 5,    /* a6 with max|T~| */
-  HOTRG_PHASE_NORM = 6   /* a7: log-norm, trace, next operands */
+  HOTRG_PHASE_ENV = 0,   /* environment halves, combine, symmetrise */
+  HOTRG_PHASE_EIGH = 1,  /* FP64 leading eigenpairs of M */
+  HOTRG_PHASE_PROJ = 2,  /* spectrum, truncation, projector layouts */
+  HOTRG_PHASE_C1 = 3,    /* X1 = U T */
+  HOTRG_PHASE_C2 = 4,    /* X2 = X1 T: the O(D^7) contraction */
+  HOTRG_PHASE_C3 = 5,    /* T~ = X2 U, with max|T~| */
+  HOTRG_PHASE_NORM = 6   /* log-norm, trace, next operands */
 };
 typedef struct {
   int step;   /* 1-based step index within its state */
@@ -178,18 +178,20 @@ hotrg_status hotrg_ctx_enable_timing(hotrg_ctx* ctx, int on);
 int hotrg_ctx_timings(hotrg_ctx* ctx, hotrg_phase_time* out, int cap);
 
 /* ---- primitive contractions on caller device buffers (same kernels) -----
- * All pointers are device pointers of FP64 arrays, row-major.  They run on
- * the context's stream and return without waiting for it. */
+ * All pointers are device pointers of FP64 arrays, row-major; `prec`
+ * selects the arithmetic of the contractions (inputs are rounded to it,
+ * results are returned as FP64).  They wait for the context's stream. */
 
-/* a1+a2: M[(i,j),(k,l)] = sum T[j,a,b,e] T[i,e,c,d] T[l,a,b,f] T[k,f,c,d]
+/* Environment: M[(i,j),(k,l)] = sum T[j,a,b,e] T[i,e,c,d] T[l,a,b,f] T[k,f,c,d]
  * (Sec. 2), T of shape (dx,dy,dx,dy), M of shape (dx*dx, dx*dx). */
-hotrg_status hotrg_environment(hotrg_ctx* ctx, const double* T, int dx, int dy, double* M);
+hotrg_status hotrg_environment(hotrg_ctx* ctx, int prec, const double* T, int dx, int dy,
+                               double* M);
 
-/* a4..a6: Tt[i,j,k,l] = sum U[a,b,i] T[b,j,d,c] T[a,c,e,l] U[e,d,k] (Sec. 2),
- * T (dx,dy,dx,dy), U (dx,dx,dn), Tt (dn,dy,dn,dy); *max_abs (device,
- * may be NULL) receives max|Tt|. */
-hotrg_status hotrg_coarse(hotrg_ctx* ctx, const double* T, const double* U, int dx, int dy, int dn,
-                          double* Tt, double* max_abs);
+/* Coarse tensor: Tt[i,j,k,l] = sum U[a,b,i] T[b,j,d,c] T[a,c,e,l] U[e,d,k]
+ * (Sec. 2), T (dx,dy,dx,dy), U (dx,dx,dn), Tt (dn,dy,dn,dy); *max_abs
+ * (device, may be NULL) receives max|Tt|. */
+hotrg_status hotrg_coarse(hotrg_ctx* ctx, int prec, const double* T, const double* U, int dx,
+                          int dy, int dn, double* Tt, double* max_abs);
 
 #ifdef __cplusplus
 }

@@ -91,8 +91,8 @@ def lib():
     L.hotrg_state_free.argtypes = [vp, vp]
     L.hotrg_state_free.restype = None
     L.hotrg_run.argtypes = [vp, POINTER(ModelParams), POINTER(Opts), POINTER(Result)]
-    L.hotrg_environment.argtypes = [vp, vp, c_int, c_int, vp]
-    L.hotrg_coarse.argtypes = [vp, vp, vp, c_int, c_int, c_int, vp, vp]
+    L.hotrg_environment.argtypes = [vp, c_int, vp, c_int, c_int, vp]
+    L.hotrg_coarse.argtypes = [vp, c_int, vp, vp, c_int, c_int, c_int, vp, vp]
     L.hotrg_ctx_enable_timing.argtypes = [vp, c_int]
     L.hotrg_ctx_timings.argtypes = [vp, POINTER(PhaseTime), c_int]
     for name in EXPORTS:
@@ -182,7 +182,7 @@ class Context:
 
 
 def hotrg_run(ctx, params, opts):
-    """a0..a8.  Returns dict(lnz_per_site, steps=[dict], spectra=(n_steps, spec_len), seconds)."""
+    """Whole run.  Returns dict(lnz_per_site, steps=[dict], spectra=(n_steps, spec_len), seconds)."""
     K = opts.n_steps
     infos = (StepInfo * max(K, 1))()
     spec = np.zeros((max(K, 1), max(opts.spec_len, 1)), dtype=np.float64)
@@ -241,15 +241,20 @@ class State:
             pass
 
 
-def hotrg_environment(ctx, T, M):
-    """a1+a2 on device buffers: T (dx,dy,dx,dy) float64 CUDA tensor -> M (dx^2, dx^2)."""
+def _prec(p):
+    return PREC[p] if isinstance(p, str) else int(p)
+
+
+def hotrg_environment(ctx, T, M, prec="fp64"):
+    """Environment on device buffers: T (dx,dy,dx,dy) float64 tensor -> M (dx^2, dx^2)."""
     dx, dy = T.shape[0], T.shape[1]
-    _check(lib().hotrg_environment(ctx.ptr, c_void_p(T.data_ptr()), dx, dy, c_void_p(M.data_ptr())))
+    _check(lib().hotrg_environment(ctx.ptr, _prec(prec), c_void_p(T.data_ptr()), dx, dy,
+                                   c_void_p(M.data_ptr())))
 
 
-def hotrg_coarse(ctx, T, U, Tt, max_abs=None):
-    """a4..a6 on device buffers: T (dx,dy,dx,dy), U (dx,dx,dn) -> Tt (dn,dy,dn,dy)."""
+def hotrg_coarse(ctx, T, U, Tt, max_abs=None, prec="fp64"):
+    """Coarse tensor on device buffers: T (dx,dy,dx,dy), U (dx,dx,dn) -> Tt (dn,dy,dn,dy)."""
     dx, dy, dn = T.shape[0], T.shape[1], U.shape[2]
-    _check(lib().hotrg_coarse(ctx.ptr, c_void_p(T.data_ptr()), c_void_p(U.data_ptr()), dx, dy, dn,
-                              c_void_p(Tt.data_ptr()),
+    _check(lib().hotrg_coarse(ctx.ptr, _prec(prec), c_void_p(T.data_ptr()), c_void_p(U.data_ptr()),
+                              dx, dy, dn, c_void_p(Tt.data_ptr()),
                               c_void_p(max_abs.data_ptr()) if max_abs is not None else None))

@@ -209,7 +209,7 @@ bool topk_eigs(rocblas_handle blas, const double* M, int n, int p, int need, dou
            hipSuccess;
   }();
   if (!lds_set || p > 128) return false;
-  hipMemsetAsync(fail, 0, sizeof(int), s);
+  (void)hipMemsetAsync(fail, 0, sizeof(int), s);
   hipLaunchKernelGGL(k_seed_block, dim3(256), dim3(256), 0, s, V, (long long)pn, 12345ULL);
 
   // one orthonormalisation of rows of Y into V
@@ -248,10 +248,10 @@ bool topk_eigs(rocblas_handle blas, const double* M, int n, int p, int need, dou
     gemm_f64(H, p, Y, n, B_NCONTIG, Yx, out_rowmajor(n), p, n, p, nullptr, s);
     hipLaunchKernelGGL(k_ritz_residual, dim3(p), dim3(256), 0, s, Yx, Xout, W, n, res);
     int hinfo[2] = {0, 0};
-    hipMemcpyAsync(th.data(), W, p * sizeof(double), hipMemcpyDeviceToHost, s);
-    hipMemcpyAsync(rs.data(), res, p * sizeof(double), hipMemcpyDeviceToHost, s);
-    hipMemcpyAsync(&hinfo[0], dinfo, sizeof(int), hipMemcpyDeviceToHost, s);
-    hipMemcpyAsync(&hinfo[1], fail, sizeof(int), hipMemcpyDeviceToHost, s);
+    (void)hipMemcpyAsync(th.data(), W, p * sizeof(double), hipMemcpyDeviceToHost, s);
+    (void)hipMemcpyAsync(rs.data(), res, p * sizeof(double), hipMemcpyDeviceToHost, s);
+    (void)hipMemcpyAsync(&hinfo[0], dinfo, sizeof(int), hipMemcpyDeviceToHost, s);
+    (void)hipMemcpyAsync(&hinfo[1], fail, sizeof(int), hipMemcpyDeviceToHost, s);
     if (hipStreamSynchronize(s) != hipSuccess) return false;
     if (hinfo[0] != 0 || hinfo[1] != 0) return false;
     const double t1 = th[p - 1];
@@ -268,7 +268,7 @@ bool topk_eigs(rocblas_handle blas, const double* M, int n, int p, int need, dou
     q = (int)std::ceil(std::log(tol / top) / std::log(rate));
     q = q < 1 ? 1 : (q > max_it - it ? max_it - it : q);
     // continue from the Ritz vectors
-    hipMemcpyAsync(V, Xout, pn * sizeof(double), hipMemcpyDeviceToDevice, s);
+    (void)hipMemcpyAsync(V, Xout, pn * sizeof(double), hipMemcpyDeviceToDevice, s);
   }
 }
 

@@ -65,6 +65,8 @@ struct hotrg_ctx {
   rocblas_handle blas = nullptr;
   // step workspace, grown on demand
   Buf A1, A2, M, W, E, Ucan, U1, U3, X1, X2, Tt, scal, EW, Xr;
+  // reduced-precision workspace: [0] hi / float, [1] lo (split bf16 only)
+  Buf RA1[2], RA2[2], RX1[2], RX2[2], RU1[2], RU3[2];
   // scal layout (bytes): 0 maxbits (u64), 8 info (int), 16 kept (int), 24 finish out (double),
   // 32 primitive max (u64), 40 trace(M) (double), 48 iterative solver info (int)
   int last_eig_iters = 0;      // sweeps of the last iterative solve (0: dense solver)
@@ -84,7 +86,13 @@ struct hotrg_ctx {
 struct hotrg_state {
   int prec = HOTRG_FP64;
   int dx = 0, dy = 0, k = 0;
-  Buf Tn, Xt, Tp;      // operands of the next step (normalised)
+  // current normalised tensor: Tn (FP64) when !cur_f32, Tn32 (FP32) otherwise
+  bool cur_f32 = false;
+  Buf Tn32;
+  // precision the operands below were prepared for
+  int ops_prec = HOTRG_FP64;
+  Buf Tn, Xt, Tp;      // FP64 operands of the next step (normalised)
+  Buf RO[4][2];        // reduced-precision operands OT, OX, OC1, OC2 ([.][0] hi/float, [.][1] lo)
   Buf acc;             // device double: ln n_0 + sum_k 2^-k ln n_k
   Buf recs;            // device: 5 doubles per step
   Buf spec;            // device spectra, spec_cap doubles per step
@@ -95,7 +103,7 @@ namespace {
 
 void ctx_free(hotrg_ctx* c, Buf& b) {
   if (b.p) {
-    hipFree(b.p);
+    (void)hipFree(b.p);
     c->in_use -= b.bytes;
     b.p = nullptr;
     b.bytes = 0;
@@ -137,7 +145,7 @@ void ensure_keep(hotrg_ctx* c, Buf& b, size_t bytes, size_t keep) {
   if (old.p) {
     if (keep) HIPCHK(hipMemcpyAsync(b.p, old.p, keep, hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
-    hipFree(old.p);
+    (void)hipFree(old.p);
     c->in_use -= old.bytes;
   }
 }
@@ -170,7 +178,6 @@ void mark(hotrg_ctx* c, int phase) {
   }
 }
 
-size_t esz(int prec) { return prec == HOTRG_FP64 ? 8 : 4; }
 
 void check_prec(int prec) {
   if (prec != HOTRG_FP64 && prec != HOTRG_FP32 && prec != HOTRG_BF16X3)
@@ -259,6 +266,9 @@ void coarse_f64(hotrg_ctx* c, const double* Tn, const double* Tp, const double* 
            (int)n, maxbits, c->stream);
 }
 
+void prepare_operands(hotrg_ctx* c, hotrg_state* st, int prec, const void* src, bool src_f32,
+                      bool rotate, int dx, int dy, const unsigned long long* mb);
+
 hotrg_state* new_state(hotrg_ctx* c, const std::vector<double>& T0, int dx, int dy, int prec) {
   for (double v : T0)
     if (!std::isfinite(v)) fail(HOTRG_ERR_NUMERIC, "initial tensor has a non-finite element");
@@ -277,11 +287,7 @@ hotrg_state* new_state(hotrg_ctx* c, const std::vector<double>& T0, int dx, int 
     HIPCHK(hipMemsetAsync(mb, 0, 8, c->stream));
     launch_maxabs(c->Tt.p, (long long)ne, false, mb, c->stream);
     launch_init_acc(mb, (double*)st->acc.p, c->stream);
-    ensure(c, st->Tn, ne * esz(prec));
-    ensure(c, st->Xt, ne * esz(prec));
-    ensure(c, st->Tp, ne * esz(prec));
-    launch_prep(c->Tt.p, false, false, dx, dy, mb, st->Tn.p, st->Xt.p, st->Tp.p,
-                prec != HOTRG_FP64, c->stream);
+    prepare_operands(c, st, HOTRG_FP64, c->Tt.p, false, false, dx, dy, mb);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->stream));
   } catch (...) {
@@ -291,12 +297,137 @@ hotrg_state* new_state(hotrg_ctx* c, const std::vector<double>& T0, int dx, int 
   return st;
 }
 
+// Precision of a step's contractions: reduced (FP32 or split BF16) only in
+// the steady state, where both legs already have the kept dimension; the
+// few warm-up steps before it stay FP64.
+int step_precision(const hotrg_state* st, int dx, int dy, int d_cut) {
+  return (st->prec != HOTRG_FP64 && dx >= d_cut && dy >= d_cut) ? st->prec : HOTRG_FP64;
+}
+
+int rp_mode(int prec) { return prec == HOTRG_FP32 ? RP_F32 : RP_BF16X3; }
+
+// Operands of a step with dims (dx, dy) in precision `prec`, from the tensor
+// `src` (FP64 or FP32; legs transposed if `rotate`; divided by the max read
+// from `mb`).  Also records the state's natural tensor in matching format.
+void prepare_operands(hotrg_ctx* c, hotrg_state* st, int prec, const void* src, bool src_f32,
+                      bool rotate, int dx, int dy, const unsigned long long* mb) {
+  const size_t ne = (size_t)dx * dy * dx * dy;
+  if (prec == HOTRG_FP64) {
+    ensure_keep(c, st->Tn, ne * 8, 0);
+    ensure_keep(c, st->Xt, ne * 8, 0);
+    ensure_keep(c, st->Tp, ne * 8, 0);
+    launch_prep(src, src_f32, rotate, dx, dy, mb, st->Tn.p, st->Xt.p, st->Tp.p, false, c->stream);
+    st->cur_f32 = false;
+  } else {
+    const int mode = rp_mode(prec);
+    const size_t es = mode == RP_F32 ? 4 : 2;
+    const long long P = (long long)dx * dy, ldP = pad32(P), ldx = pad32(dx);
+    const size_t rows[4] = {(size_t)P, (size_t)P, (size_t)dy * dx * dy, (size_t)P};
+    const size_t ld[4] = {(size_t)ldP, (size_t)ldP, (size_t)ldx, (size_t)ldP};
+    const bool padded[4] = {ldP != P, ldP != P, ldx != dx, ldP != P};
+    RpOps ops;
+    ensure_keep(c, st->Tn32, ne * 4, 0);
+    for (int i = 0; i < 4; ++i) {
+      for (int h = 0; h < (mode == RP_F32 ? 1 : 2); ++h) {
+        ensure_keep(c, st->RO[i][h], rows[i] * ld[i] * es, 0);
+        if (padded[i]) HIPCHK(hipMemsetAsync(st->RO[i][h].p, 0, rows[i] * ld[i] * es, c->stream));
+      }
+      ops.hi[i] = st->RO[i][0].p;
+      ops.lo[i] = mode == RP_F32 ? nullptr : st->RO[i][1].p;
+    }
+    launch_prep_rp(src, src_f32, rotate, dx, dy, mb, (float*)st->Tn32.p, mode, ops, ldP, ldx,
+                   c->stream);
+    st->cur_f32 = true;
+  }
+  st->ops_prec = prec;
+}
+
+void release_operands(hotrg_ctx* c, hotrg_state* st) {
+  Buf* bufs[] = {&st->Tn, &st->Xt, &st->Tp, &st->Tn32};
+  for (Buf* b : bufs) ctx_free(c, *b);
+  for (auto& o : st->RO)
+    for (auto& b : o) ctx_free(c, b);
+}
+
+// Environment M (FP64 output) from reduced-precision operands.
+void environment_rp(hotrg_ctx* c, hotrg_state* st, int mode, int dx, int dy) {
+  const long long P = (long long)dx * dy, n = (long long)dx * dx, K2 = (long long)dy * dy;
+  const long long ldP = pad32(P), ldK2 = pad32(K2);
+  const size_t es = mode == RP_F32 ? 4 : 2;
+  const int fmt = mode == RP_F32 ? RP_OUT_F32 : RP_OUT_SPLIT;
+  const int halves = mode == RP_F32 ? 1 : 2;
+  for (int h = 0; h < halves; ++h) {
+    ensure(c, c->RA1[h], (size_t)n * ldK2 * es);
+    ensure(c, c->RA2[h], (size_t)n * ldK2 * es);
+    if (ldK2 != K2) {
+      HIPCHK(hipMemsetAsync(c->RA1[h].p, 0, (size_t)n * ldK2 * es, c->stream));
+      HIPCHK(hipMemsetAsync(c->RA2[h].p, 0, (size_t)n * ldK2 * es, c->stream));
+    }
+  }
+  ensure(c, c->M, (size_t)(n * n) * 8);
+  auto op = [&](Buf* b) { return RpOperand{b[0].p, halves == 2 ? b[1].p : nullptr}; };
+  const RpOperand OT = op(st->RO[0]), OX = op(st->RO[1]);
+  // halves stored as [(i,k),(e,f)]: rows (i,e): i -> dx*ldK2, e -> dy; cols (k,f): k -> ldK2, f -> 1
+  const OutMap o2 = omap2(dy, dx * ldK2, dy, dy, ldK2, 1);
+  bool ok = gemm_rp(mode, OT, ldP, OT, ldP, fmt, c->RA2[0].p, halves == 2 ? c->RA2[1].p : nullptr,
+                    o2, (int)P, (int)P, (int)ldP, nullptr, c->stream, GEMM_TAG_ENV);
+  ok = ok && gemm_rp(mode, OX, ldP, OX, ldP, fmt, c->RA1[0].p,
+                     halves == 2 ? c->RA1[1].p : nullptr, o2, (int)P, (int)P, (int)ldP, nullptr,
+                     c->stream, GEMM_TAG_ENV);
+  const OutMap om = omap2(dx, dx * n, dx, dx, n, 1);
+  ok = ok && gemm_rp(mode, op(c->RA2), ldK2, op(c->RA1), ldK2, RP_OUT_F64, c->M.p, nullptr, om,
+                     (int)n, (int)n, (int)ldK2, nullptr, c->stream, GEMM_TAG_ENV);
+  if (!ok) fail(HOTRG_ERR_INVALID, "reduced-precision environment: unsupported operand shape");
+}
+
+// C1, C2, C3 from reduced-precision operands; T~ (FP32) into c->Tt.
+void coarse_rp(hotrg_ctx* c, hotrg_state* st, int mode, int dx, int dy, int dn,
+               unsigned long long* maxbits) {
+  const long long P = (long long)dx * dy, n = (long long)dx * dx;
+  const long long ldP = pad32(P), ldx = pad32(dx), ldn = pad32(n);
+  const size_t es = mode == RP_F32 ? 4 : 2;
+  const int fmt = mode == RP_F32 ? RP_OUT_F32 : RP_OUT_SPLIT;
+  const int halves = mode == RP_F32 ? 1 : 2;
+  const long long x1rows = (long long)dn * dy * dx, x2rows = (long long)dn * dy * dy;
+  for (int h = 0; h < halves; ++h) {
+    ensure(c, c->RX1[h], (size_t)x1rows * ldP * es);
+    ensure(c, c->RX2[h], (size_t)x2rows * ldn * es);
+    if (ldP != P) HIPCHK(hipMemsetAsync(c->RX1[h].p, 0, (size_t)x1rows * ldP * es, c->stream));
+    if (ldn != n) HIPCHK(hipMemsetAsync(c->RX2[h].p, 0, (size_t)x2rows * ldn * es, c->stream));
+  }
+  ensure(c, c->Tt, (size_t)dn * dy * dn * dy * 4);
+  auto op = [&](Buf* b) { return RpOperand{b[0].p, halves == 2 ? b[1].p : nullptr}; };
+  // C1: rows (i,a): i -> dy*dx*ldP, a -> dy; cols (j,d,c): j -> dx*ldP, d -> ldP, c -> 1
+  OutMap o1 = omap2(dx, (long long)dy * dx * ldP, dy, 1, 0, 0);
+  o1.c1 = dx;
+  o1.c2 = dy;
+  o1.t0 = (long long)dx * ldP;
+  o1.t1 = ldP;
+  o1.t2 = 1;
+  mark(c, HOTRG_PHASE_C1);
+  bool ok = gemm_rp(mode, op(c->RU1), ldx, op(st->RO[2]), ldx, fmt, c->RX1[0].p,
+                    halves == 2 ? c->RX1[1].p : nullptr, o1, dn * dx, dy * dx * dy, (int)ldx,
+                    nullptr, c->stream, GEMM_TAG_OTHER);
+  // C2: rows (ij,d): ij -> dy*ldn, d -> dx; cols (l,e): l -> ldn, e -> 1
+  const OutMap o2 = omap2(dx, (long long)dy * ldn, dx, dx, ldn, 1);
+  mark(c, HOTRG_PHASE_C2);
+  ok = ok && gemm_rp(mode, op(c->RX1), ldP, op(st->RO[3]), ldP, fmt, c->RX2[0].p,
+                     halves == 2 ? c->RX2[1].p : nullptr, o2, (int)x1rows, (int)P, (int)ldP,
+                     nullptr, c->stream, GEMM_TAG_C2);
+  // C3: rows (ij,l): ij -> dn*dy, l -> 1; cols k -> dy
+  mark(c, HOTRG_PHASE_C3);
+  HIPCHK(hipMemsetAsync(maxbits, 0, 8, c->stream));
+  const OutMap o3 = omap2(dy, (long long)dn * dy, 1, 1, dy, 0);
+  ok = ok && gemm_rp(mode, op(c->RX2), ldn, op(c->RU3), ldn, RP_OUT_F32, c->Tt.p, nullptr, o3,
+                     (int)x2rows, dn, (int)ldn, maxbits, c->stream, GEMM_TAG_OTHER);
+  if (!ok) fail(HOTRG_ERR_INVALID, "reduced-precision contraction: unsupported operand shape");
+}
+
 void do_step(hotrg_ctx* c, hotrg_state* st, const hotrg_opts* o) {
   const int dx = st->dx, dy = st->dy;
   const int n = dx * dx;
   const int dn = o->d_cut < n ? o->d_cut : n;
   check_dims(dx, dy, dn);
-  if (st->prec != HOTRG_FP64) fail(HOTRG_ERR_INVALID, "reduced precision not built yet");
   const int k = st->k + 1;
   // per-step records and spectra
   if (k > st->rec_cap) {
@@ -319,16 +450,36 @@ void do_step(hotrg_ctx* c, hotrg_state* st, const hotrg_opts* o) {
   unsigned long long* mb = (unsigned long long*)c->scal.p;
   int* info = (int*)((char*)c->scal.p + 8);
   int* kept = (int*)((char*)c->scal.p + 16);
+  unsigned long long* one = (unsigned long long*)((char*)c->scal.p + 56);
+
+  const int sp = step_precision(st, dx, dy, o->d_cut);
+  if (sp != st->ops_prec) {
+    // operands were prepared for another precision (d_cut changed): rebuild
+    const unsigned long long one_bits = 0x3ff0000000000000ULL;
+    HIPCHK(hipMemcpyAsync(one, &one_bits, 8, hipMemcpyHostToDevice, c->stream));
+    const size_t ne = (size_t)dx * dy * dx * dy;
+    Buf tmp;
+    ensure(c, tmp, ne * (st->cur_f32 ? 4 : 8));
+    HIPCHK(hipMemcpyAsync(tmp.p, st->cur_f32 ? st->Tn32.p : st->Tn.p, ne * (st->cur_f32 ? 4 : 8),
+                          hipMemcpyDeviceToDevice, c->stream));
+    const bool f32 = st->cur_f32;
+    prepare_operands(c, st, sp, tmp.p, f32, false, dx, dy, one);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    ctx_free(c, tmp);
+  }
 
   c->m_step = k;
   c->m_dx = dx;
   c->m_dy = dy;
   c->m_dn = dn;
   mark(c, HOTRG_PHASE_ENV);
-  // a1, a2: environment
-  environment_f64(c, (const double*)st->Tn.p, (const double*)st->Xt.p, dx, dy);
+  // environment M (FP64 out)
+  if (sp == HOTRG_FP64)
+    environment_f64(c, (const double*)st->Tn.p, (const double*)st->Xt.p, dx, dy);
+  else
+    environment_rp(c, st, rp_mode(sp), dx, dy);
   launch_symmetrize((double*)c->M.p, n, c->stream);
-  // a3: FP64 eigendecomposition, spectrum and projector
+  // FP64 eigendecomposition, spectrum and projector
   ensure(c, c->W, (size_t)n * 8);
   ensure(c, c->E, (size_t)n * 8);
   double* trace = (double*)((char*)c->scal.p + 40);
@@ -369,22 +520,36 @@ void do_step(hotrg_ctx* c, hotrg_state* st, const hotrg_opts* o) {
   launch_spectrum((const double*)c->W.p, cols, n, dn, o->trunc, o->degen_tol, st->spec_len,
                   trace, spec, rec, kept, c->stream);
   ensure(c, c->Ucan, (size_t)n * dn * 8);
-  ensure(c, c->U1, (size_t)n * dn * 8);
-  ensure(c, c->U3, (size_t)n * dn * 8);
   launch_isometry(evec, cols, n, dn, kept, (double*)c->Ucan.p, c->stream);
-  launch_layout_u((const double*)c->Ucan.p, dx, dn, c->U1.p, c->U3.p, false, c->stream);
-  // a4..a6: the three contractions, max|T~|
-  coarse_f64(c, (const double*)st->Tn.p, (const double*)st->Tp.p, (const double*)c->U1.p,
-             (const double*)c->U3.p, dx, dy, dn, mb);
-  // a7: ln n_k, torus estimate; operands of the next step (legs transposed)
+  if (sp == HOTRG_FP64) {
+    ensure(c, c->U1, (size_t)n * dn * 8);
+    ensure(c, c->U3, (size_t)n * dn * 8);
+    launch_layout_u((const double*)c->Ucan.p, dx, dn, c->U1.p, c->U3.p, false, c->stream);
+    // the three contractions, max|T~|
+    coarse_f64(c, (const double*)st->Tn.p, (const double*)st->Tp.p, (const double*)c->U1.p,
+               (const double*)c->U3.p, dx, dy, dn, mb);
+  } else {
+    const int mode = rp_mode(sp);
+    const size_t es = mode == RP_F32 ? 4 : 2;
+    const long long ldx = pad32(dx), ldn = pad32(n);
+    for (int h = 0; h < (mode == RP_F32 ? 1 : 2); ++h) {
+      ensure(c, c->RU1[h], (size_t)dn * dx * ldx * es);
+      ensure(c, c->RU3[h], (size_t)dn * ldn * es);
+      if (ldx != dx) HIPCHK(hipMemsetAsync(c->RU1[h].p, 0, (size_t)dn * dx * ldx * es, c->stream));
+      if (ldn != n) HIPCHK(hipMemsetAsync(c->RU3[h].p, 0, (size_t)dn * ldn * es, c->stream));
+    }
+    launch_layout_u_rp((const double*)c->Ucan.p, dx, dn, mode, c->RU1[0].p,
+                       mode == RP_F32 ? nullptr : c->RU1[1].p, c->RU3[0].p,
+                       mode == RP_F32 ? nullptr : c->RU3[1].p, ldx, ldn, c->stream);
+    coarse_rp(c, st, mode, dx, dy, dn, mb);
+  }
+  // ln n_k, torus estimate; operands of the next step (legs transposed)
   mark(c, HOTRG_PHASE_NORM);
-  launch_norm(mb, c->Tt.p, false, dn, dy, std::ldexp(1.0, -k), (double*)st->acc.p, rec, c->stream);
+  const bool tt_f32 = sp != HOTRG_FP64;
+  launch_norm(mb, c->Tt.p, tt_f32, dn, dy, std::ldexp(1.0, -k), (double*)st->acc.p, rec, c->stream);
   const int ndx = dy, ndy = dn;
-  const size_t ne = (size_t)ndx * ndy * ndx * ndy;
-  ensure_keep(c, st->Tn, ne * 8, 0);
-  ensure_keep(c, st->Xt, ne * 8, 0);
-  ensure_keep(c, st->Tp, ne * 8, 0);
-  launch_prep(c->Tt.p, false, true, ndx, ndy, mb, st->Tn.p, st->Xt.p, st->Tp.p, false, c->stream);
+  const int nsp = step_precision(st, ndx, ndy, o->d_cut);
+  prepare_operands(c, st, nsp, c->Tt.p, tt_f32, true, ndx, ndy, mb);
   mark(c, -1);
   HIPCHK(hipGetLastError());
   st->dx = ndx;
@@ -494,7 +659,7 @@ hotrg_status hotrg_ctx_create(int device, void* hip_stream, size_t hbm_budget, h
       c->own_stream = true;
     }
     if (rocblas_create_handle(&c->blas) != rocblas_status_success) {
-      if (c->own_stream) hipStreamDestroy(c->stream);
+      if (c->own_stream) (void)hipStreamDestroy(c->stream);
       delete c;
       fail(HOTRG_ERR_DEVICE, "rocblas_create_handle failed");
     }
@@ -505,20 +670,22 @@ hotrg_status hotrg_ctx_create(int device, void* hip_stream, size_t hbm_budget, h
 
 void hotrg_ctx_destroy(hotrg_ctx* c) {
   if (!c) return;
-  hipSetDevice(c->device);
-  hipStreamSynchronize(c->stream);
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
   Buf* bufs[] = {&c->A1, &c->A2, &c->M, &c->W, &c->E, &c->Ucan, &c->U1, &c->U3,
                  &c->X1, &c->X2, &c->Tt, &c->scal, &c->EW, &c->Xr};
   for (Buf* b : bufs) ctx_free(c, *b);
+  for (Buf* arr : {c->RA1, c->RA2, c->RX1, c->RX2, c->RU1, c->RU3})
+    for (int h = 0; h < 2; ++h) ctx_free(c, arr[h]);
   for (auto& m : c->marks) {
     c->pool.push_back(m.a);
     c->pool.push_back(m.b);
   }
   std::sort(c->pool.begin(), c->pool.end());
   c->pool.erase(std::unique(c->pool.begin(), c->pool.end()), c->pool.end());
-  for (hipEvent_t e : c->pool) hipEventDestroy(e);
+  for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
   if (c->blas) rocblas_destroy_handle(c->blas);
-  if (c->own_stream) hipStreamDestroy(c->stream);
+  if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
 
@@ -569,8 +736,8 @@ hotrg_status hotrg_finish(hotrg_ctx* c, hotrg_state* st, double* lnz) {
     HIPCHK(hipSetDevice(c->device));
     ensure(c, c->scal, 64);
     double* outp = (double*)((char*)c->scal.p + 24);
-    launch_finish(st->Tn.p, st->prec != HOTRG_FP64, st->dx, st->dy, std::ldexp(1.0, -st->k),
-                  (const double*)st->acc.p, outp, c->stream);
+    launch_finish(st->cur_f32 ? st->Tn32.p : st->Tn.p, st->cur_f32, st->dx, st->dy,
+                  std::ldexp(1.0, -st->k), (const double*)st->acc.p, outp, c->stream);
     HIPCHK(hipGetLastError());
     double v = 0;
     HIPCHK(hipMemcpyAsync(&v, outp, 8, hipMemcpyDeviceToHost, c->stream));
@@ -589,11 +756,11 @@ hotrg_status hotrg_state_export(hotrg_ctx* c, const hotrg_state* st, double* hos
     size_t ne = (size_t)st->dx * st->dy * st->dx * st->dy;
     if (host && cap < ne) fail(HOTRG_ERR_INVALID, "host buffer too small");
     if (host) {
-      if (st->prec == HOTRG_FP64) {
+      if (!st->cur_f32) {
         HIPCHK(hipMemcpyAsync(host, st->Tn.p, ne * 8, hipMemcpyDeviceToHost, c->stream));
       } else {
         std::vector<float> f(ne);
-        HIPCHK(hipMemcpyAsync(f.data(), st->Tn.p, ne * 4, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipMemcpyAsync(f.data(), st->Tn32.p, ne * 4, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
         for (size_t i = 0; i < ne; ++i) host[i] = f[i];
       }
@@ -612,10 +779,12 @@ hotrg_status hotrg_state_export(hotrg_ctx* c, const hotrg_state* st, double* hos
 
 void hotrg_state_free(hotrg_ctx* c, hotrg_state* st) {
   if (!c || !st) return;
-  hipSetDevice(c->device);
-  hipStreamSynchronize(c->stream);
-  Buf* bufs[] = {&st->Tn, &st->Xt, &st->Tp, &st->acc, &st->recs, &st->spec};
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  Buf* bufs[] = {&st->Tn, &st->Xt, &st->Tp, &st->acc, &st->recs, &st->spec, &st->Tn32};
   for (Buf* b : bufs) ctx_free(c, *b);
+  for (auto& o : st->RO)
+    for (auto& b : o) ctx_free(c, b);
   delete st;
 }
 
@@ -692,69 +861,98 @@ int hotrg_ctx_timings(hotrg_ctx* c, hotrg_phase_time* out, int cap) {
   return s == HOTRG_OK ? n : -1;
 }
 
-hotrg_status hotrg_environment(hotrg_ctx* c, const double* T, int dx, int dy, double* M) {
+hotrg_status hotrg_environment(hotrg_ctx* c, int prec, const double* T, int dx, int dy,
+                               double* M) {
   return guard([&] {
     if (!c || !T || !M) fail(HOTRG_ERR_INVALID, "NULL argument");
     if (dx < 1 || dy < 1) fail(HOTRG_ERR_INVALID, "dx, dy must be >= 1");
+    check_prec(prec);
     check_dims(dx, dy, 1);
     HIPCHK(hipSetDevice(c->device));
-    const size_t ne = (size_t)dx * dy * dx * dy;
-    // Xt from T (no rotation, no scaling: maxbits = 1.0)
     ensure(c, c->scal, 64);
-    unsigned long long one = (unsigned long long)0x3ff0000000000000ULL;
-    HIPCHK(hipMemcpyAsync(c->scal.p, &one, 8, hipMemcpyHostToDevice, c->stream));
-    ensure(c, c->Ucan, ne * 8);  // scratch for Xt
-    ensure(c, c->U1, ne * 8);    // scratch for Tn copy
-    ensure(c, c->U3, ne * 8);    // scratch for Tp
-    launch_prep(T, false, false, dx, dy, (const unsigned long long*)c->scal.p, c->U1.p, c->Ucan.p,
-                c->U3.p, false, c->stream);
-    c->m_step = 0;
-    c->m_dx = dx;
-    c->m_dy = dy;
-    c->m_dn = dx * dx;
-    mark(c, HOTRG_PHASE_ENV);
-    environment_f64(c, (const double*)c->U1.p, (const double*)c->Ucan.p, dx, dy);
-    mark(c, -1);
-    const size_t nn = (size_t)dx * dx * dx * dx;
-    HIPCHK(hipMemcpyAsync(M, c->M.p, nn * 8, hipMemcpyDeviceToDevice, c->stream));
-    HIPCHK(hipGetLastError());
-    HIPCHK(hipStreamSynchronize(c->stream));
+    unsigned long long* one = (unsigned long long*)((char*)c->scal.p + 56);
+    const unsigned long long one_bits = 0x3ff0000000000000ULL;
+    HIPCHK(hipMemcpyAsync(one, &one_bits, 8, hipMemcpyHostToDevice, c->stream));
+    hotrg_state tmp;  // operands only, freed below
+    try {
+      prepare_operands(c, &tmp, prec, T, false, false, dx, dy, one);
+      c->m_step = 0;
+      c->m_dx = dx;
+      c->m_dy = dy;
+      c->m_dn = dx * dx;
+      mark(c, HOTRG_PHASE_ENV);
+      if (prec == HOTRG_FP64)
+        environment_f64(c, (const double*)tmp.Tn.p, (const double*)tmp.Xt.p, dx, dy);
+      else
+        environment_rp(c, &tmp, rp_mode(prec), dx, dy);
+      mark(c, -1);
+      const size_t nn = (size_t)dx * dx * dx * dx;
+      HIPCHK(hipMemcpyAsync(M, c->M.p, nn * 8, hipMemcpyDeviceToDevice, c->stream));
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipStreamSynchronize(c->stream));
+    } catch (...) {
+      release_operands(c, &tmp);
+      throw;
+    }
+    release_operands(c, &tmp);
   });
 }
 
-hotrg_status hotrg_coarse(hotrg_ctx* c, const double* T, const double* U, int dx, int dy, int dn,
-                          double* Tt, double* max_abs) {
+hotrg_status hotrg_coarse(hotrg_ctx* c, int prec, const double* T, const double* U, int dx,
+                          int dy, int dn, double* Tt, double* max_abs) {
   return guard([&] {
     if (!c || !T || !U || !Tt) fail(HOTRG_ERR_INVALID, "NULL argument");
     if (dx < 1 || dy < 1 || dn < 1) fail(HOTRG_ERR_INVALID, "dims must be >= 1");
+    check_prec(prec);
     check_dims(dx, dy, dn);
     HIPCHK(hipSetDevice(c->device));
-    const size_t ne = (size_t)dx * dy * dx * dy;
     ensure(c, c->scal, 64);
-    unsigned long long one = (unsigned long long)0x3ff0000000000000ULL;
-    HIPCHK(hipMemcpyAsync(c->scal.p, &one, 8, hipMemcpyHostToDevice, c->stream));
-    ensure(c, c->A1, ne * 8);  // Tn
-    ensure(c, c->A2, ne * 8);  // Xt (unused)
-    ensure(c, c->M, ne * 8);   // Tp
-    launch_prep(T, false, false, dx, dy, (const unsigned long long*)c->scal.p, c->A1.p, c->A2.p,
-                c->M.p, false, c->stream);
-    const size_t nu = (size_t)dx * dx * dn;
-    ensure(c, c->U1, nu * 8);
-    ensure(c, c->U3, nu * 8);
-    launch_layout_u(U, dx, dn, c->U1.p, c->U3.p, false, c->stream);
+    unsigned long long* one = (unsigned long long*)((char*)c->scal.p + 56);
+    const unsigned long long one_bits = 0x3ff0000000000000ULL;
+    HIPCHK(hipMemcpyAsync(one, &one_bits, 8, hipMemcpyHostToDevice, c->stream));
     unsigned long long* mb = (unsigned long long*)c->scal.p + 4;
-    c->m_step = 0;
-    c->m_dx = dx;
-    c->m_dy = dy;
-    c->m_dn = dn;
-    coarse_f64(c, (const double*)c->A1.p, (const double*)c->M.p, (const double*)c->U1.p,
-               (const double*)c->U3.p, dx, dy, dn, mb);
-    mark(c, -1);
-    const size_t no = (size_t)dn * dy * dn * dy;
-    HIPCHK(hipMemcpyAsync(Tt, c->Tt.p, no * 8, hipMemcpyDeviceToDevice, c->stream));
-    if (max_abs) HIPCHK(hipMemcpyAsync(max_abs, mb, 8, hipMemcpyDeviceToDevice, c->stream));
-    HIPCHK(hipGetLastError());
-    HIPCHK(hipStreamSynchronize(c->stream));
+    hotrg_state tmp;
+    try {
+      prepare_operands(c, &tmp, prec, T, false, false, dx, dy, one);
+      c->m_step = 0;
+      c->m_dx = dx;
+      c->m_dy = dy;
+      c->m_dn = dn;
+      const size_t no = (size_t)dn * dy * dn * dy;
+      if (prec == HOTRG_FP64) {
+        const size_t nu = (size_t)dx * dx * dn;
+        ensure(c, c->U1, nu * 8);
+        ensure(c, c->U3, nu * 8);
+        launch_layout_u(U, dx, dn, c->U1.p, c->U3.p, false, c->stream);
+        coarse_f64(c, (const double*)tmp.Tn.p, (const double*)tmp.Tp.p, (const double*)c->U1.p,
+                   (const double*)c->U3.p, dx, dy, dn, mb);
+        mark(c, -1);
+        HIPCHK(hipMemcpyAsync(Tt, c->Tt.p, no * 8, hipMemcpyDeviceToDevice, c->stream));
+      } else {
+        const int mode = rp_mode(prec);
+        const size_t es = mode == RP_F32 ? 4 : 2;
+        const long long n = (long long)dx * dx, ldx = pad32(dx), ldn = pad32(n);
+        for (int h = 0; h < (mode == RP_F32 ? 1 : 2); ++h) {
+          ensure(c, c->RU1[h], (size_t)dn * dx * ldx * es);
+          ensure(c, c->RU3[h], (size_t)dn * ldn * es);
+          HIPCHK(hipMemsetAsync(c->RU1[h].p, 0, (size_t)dn * dx * ldx * es, c->stream));
+          HIPCHK(hipMemsetAsync(c->RU3[h].p, 0, (size_t)dn * ldn * es, c->stream));
+        }
+        launch_layout_u_rp(U, dx, dn, mode, c->RU1[0].p, mode == RP_F32 ? nullptr : c->RU1[1].p,
+                           c->RU3[0].p, mode == RP_F32 ? nullptr : c->RU3[1].p, ldx, ldn,
+                           c->stream);
+        coarse_rp(c, &tmp, mode, dx, dy, dn, mb);
+        mark(c, -1);
+        launch_f32_to_f64((const float*)c->Tt.p, Tt, (long long)no, c->stream);
+      }
+      if (max_abs) HIPCHK(hipMemcpyAsync(max_abs, mb, 8, hipMemcpyDeviceToDevice, c->stream));
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipStreamSynchronize(c->stream));
+    } catch (...) {
+      release_operands(c, &tmp);
+      throw;
+    }
+    release_operands(c, &tmp);
   });
 }
 

@@ -1,0 +1,258 @@
+// Reduced-precision contractions of the HOTRG step: FP32 MFMA, or split
+// BF16 with three products and FP32 accumulation.
+//
+//   C[map(m, n)] = sum_k A[m][k] * B[n][k]      (both operands K-contiguous)
+//
+// Operand formats (rows of ldk elements, ldk a multiple of 32, entries past
+// the true K are zero):
+//   RP_F32    one float array;
+//   RP_BF16X3 two bf16 arrays hi, lo with x = hi + lo + O(2^-16 |x|):
+//             hi = bf16(x), lo = bf16(x - hi), both round-to-nearest.
+//             a*b is taken as lo_a*hi_b + hi_a*lo_b + hi_a*hi_b (the lo*lo
+//             term, O(2^-16), is dropped), products exact, sums in FP32.
+// Output: FP32, split BF16 (for a following BF16X3 contraction) or FP64
+// (for the FP64 eigensolver).
+//
+// Tiling: 8 waves, 256 x 128 block tile, each wave 64 x 64 as 4 x 4 MFMA
+// tiles; K slabs of 32 elements streamed into LDS with
+// global_load_lds_dwordx4 (16 bytes per lane), two LDS stages.  An LDS row
+// is 128 bytes = 8 chunks of 16 bytes: for RP_F32 the 32 floats of the slab,
+// for RP_BF16X3 four hi chunks then four lo chunks (8 bf16 each).  Chunk c
+// of row r sits at chunk position c ^ ((r >> 1) & 7), so the 16 rows read by
+// one 16-lane group fall into distinct LDS banks.
+//
+// MFMA lane layouts (gfx950): f32_16x16x4f32 and f32_16x16x32_bf16 both
+// take A[i][k] from lane i + 16 g and return D[4 g + v][i] in value v of
+// lane i + 16 g; the bf16 form takes 8 consecutive k per lane.  For FP32
+// the 32 k of a slab are split by lane group: group g owns k in [8g, 8g+8),
+// one k per MFMA; for BF16 group g owns the same 8 k in one MFMA.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace hotrg {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef __attribute__((address_space(3))) void lds_void_rp;
+
+__device__ __forceinline__ long long rmap_row(const OutMap& o, int m) {
+  int m2 = m % o.r2;
+  int q = m / o.r2;
+  int m1 = q % o.r1;
+  int m0 = q / o.r1;
+  return (long long)m0 * o.s0 + (long long)m1 * o.s1 + (long long)m2 * o.s2;
+}
+
+__device__ __forceinline__ long long rmap_col(const OutMap& o, int n) {
+  int n2 = n % o.c2;
+  int q = n / o.c2;
+  int n1 = q % o.c1;
+  int n0 = q / o.c1;
+  return (long long)n0 * o.t0 + (long long)n1 * o.t1 + (long long)n2 * o.t2;
+}
+
+__device__ __forceinline__ int rp_swz(int r) { return (r >> 1) & 7; }
+
+// Stream rows [row0, row0 + R) x slab [k0, k0 + 32) of an operand into LDS.
+// One wave instruction moves 8 rows (1 KB).
+template <int R, int MODE>
+__device__ __forceinline__ void rp_load(const void* __restrict__ hi, const void* __restrict__ lo,
+                                        long long ldk, int row0, int rows_valid, int k0, char* lds,
+                                        int wave, int lane) {
+  constexpr int INSTS = R / 8;
+  static_assert(INSTS % 8 == 0, "instructions must split over 8 waves");
+#pragma unroll
+  for (int q = 0; q < INSTS / 8; ++q) {
+    const int inst = wave + q * 8;
+    const int r = inst * 8 + lane / 8;
+    const int c = lane % 8;
+    const int g = c ^ rp_swz(r);  // chunk stored at position c
+    int gr = row0 + r;
+    gr = gr < rows_valid ? gr : rows_valid - 1;
+    const char* src;
+    if (MODE == RP_F32)
+      src = (const char*)hi + ((long long)gr * ldk + k0 + 4 * g) * 4;
+    else
+      src = (const char*)(g < 4 ? hi : lo) + ((long long)gr * ldk + k0 + 8 * (g & 3)) * 2;
+    __builtin_amdgcn_global_load_lds((const void*)src, (lds_void_rp*)(lds + inst * 1024), 16, 0, 0);
+  }
+}
+
+template <int MODE, int OUT, int TAG>
+__global__ __launch_bounds__(512) void k_gemm_rp(const void* __restrict__ Ahi,
+                                                 const void* __restrict__ Alo, long long lda,
+                                                 const void* __restrict__ Bhi,
+                                                 const void* __restrict__ Blo, long long ldb,
+                                                 void* __restrict__ C, void* __restrict__ Clo,
+                                                 OutMap om, int M, int N, int K,
+                                                 unsigned long long* maxbits) {
+  constexpr int BM = 256, BN = 128, A_BYTES = BM * 128, B_BYTES = BN * 128;
+  constexpr int STAGE = A_BYTES + B_BYTES;
+  constexpr int LOADS = BM / 64 + BN / 64;  // per wave per slab
+  __shared__ __attribute__((aligned(16))) char smem[2 * STAGE];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int li = lane & 15, lg = lane >> 4;
+
+  f4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+
+  auto issue = [&](int k0, int stage) {
+    char* base = smem + stage * STAGE;
+    rp_load<BM, MODE>(Ahi, Alo, lda, m0, M, k0, base, wave, lane);
+    rp_load<BN, MODE>(Bhi, Blo, ldb, n0, N, k0, base + A_BYTES, wave, lane);
+  };
+  // the two 16-byte chunks a lane group reads from a row
+  const int c0 = MODE == RP_F32 ? 2 * lg : lg;
+  const int c1 = MODE == RP_F32 ? 2 * lg + 1 : 4 + lg;
+
+  const int nslab = K / 32;
+  issue(0, 0);
+  for (int s = 0; s < nslab; ++s) {
+    const int cur = s & 1;
+    if (s + 1 < nslab) {
+      issue((s + 1) * 32, cur ^ 1);
+      asm volatile("s_waitcnt vmcnt(%0)" ::"n"(LOADS) : "memory");
+    } else {
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    }
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    const char* as = smem + cur * STAGE;
+    const char* bs = as + A_BYTES;
+    f4 a0[4], a1[4], b0[4], b1[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = wm * 64 + i * 16 + li;
+      a0[i] = *(const f4*)(as + r * 128 + ((c0 ^ rp_swz(r)) << 4));
+      a1[i] = *(const f4*)(as + r * 128 + ((c1 ^ rp_swz(r)) << 4));
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r = wn * 64 + j * 16 + li;
+      b0[j] = *(const f4*)(bs + r * 128 + ((c0 ^ rp_swz(r)) << 4));
+      b1[j] = *(const f4*)(bs + r * 128 + ((c1 ^ rp_swz(r)) << 4));
+    }
+    if (MODE == RP_F32) {
+#pragma unroll
+      for (int t = 0; t < 8; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const float av = t < 4 ? a0[i][t] : a1[i][t - 4];
+            const float bv = t < 4 ? b0[j][t] : b1[j][t - 4];
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[i][j], 0, 0, 0);
+          }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const bf8 ah = __builtin_bit_cast(bf8, a0[i]);
+        const bf8 al = __builtin_bit_cast(bf8, a1[i]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const bf8 bh = __builtin_bit_cast(bf8, b0[j]);
+          const bf8 bl = __builtin_bit_cast(bf8, b1[j]);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[i][j], 0, 0, 0);
+        }
+      }
+    }
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+  }
+
+  float mx = 0.f;
+  long long coff[4];
+  bool cok[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int n = n0 + wn * 64 + j * 16 + li;
+    cok[j] = n < N;
+    coff[j] = cok[j] ? rmap_col(om, n) : 0;
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int m = m0 + wm * 64 + i * 16 + 4 * lg + v;
+      if (m >= M) continue;
+      const long long roff = rmap_row(om, m);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (!cok[j]) continue;
+        const float x = acc[i][j][v];
+        const long long o = roff + coff[j];
+        if (OUT == RP_OUT_F32) {
+          ((float*)C)[o] = x;
+        } else if (OUT == RP_OUT_F64) {
+          ((double*)C)[o] = (double)x;
+        } else {
+          const __bf16 h = (__bf16)x;
+          ((__bf16*)C)[o] = h;
+          ((__bf16*)Clo)[o] = (__bf16)(x - (float)h);
+        }
+        mx = fmaxf(mx, fabsf(x));
+      }
+    }
+  }
+  if (maxbits) {
+    double m = mx;
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    if (lane == 0) atomicMax(maxbits, (unsigned long long)__double_as_longlong(m));
+  }
+}
+
+template <int MODE, int OUT>
+static void launch_rp_tag(int tag, const RpOperand& A, long long lda, const RpOperand& B,
+                          long long ldb, void* C, void* Clo, const OutMap& om, int M, int N,
+                          int K, unsigned long long* maxbits, hipStream_t s) {
+  dim3 grid((N + 127) / 128, (M + 255) / 256);
+  if (tag == GEMM_TAG_C2)
+    hipLaunchKernelGGL((k_gemm_rp<MODE, OUT, GEMM_TAG_C2>), grid, dim3(512), 0, s, A.hi, A.lo, lda,
+                       B.hi, B.lo, ldb, C, Clo, om, M, N, K, maxbits);
+  else if (tag == GEMM_TAG_ENV)
+    hipLaunchKernelGGL((k_gemm_rp<MODE, OUT, GEMM_TAG_ENV>), grid, dim3(512), 0, s, A.hi, A.lo,
+                       lda, B.hi, B.lo, ldb, C, Clo, om, M, N, K, maxbits);
+  else
+    hipLaunchKernelGGL((k_gemm_rp<MODE, OUT, GEMM_TAG_OTHER>), grid, dim3(512), 0, s, A.hi, A.lo,
+                       lda, B.hi, B.lo, ldb, C, Clo, om, M, N, K, maxbits);
+}
+
+bool gemm_rp(int mode, const RpOperand& A, long long lda, const RpOperand& B, long long ldb,
+             int out, void* C, void* Clo, const OutMap& om, int M, int N, int K,
+             unsigned long long* maxbits, hipStream_t s, int tag) {
+  if (M < 1 || N < 1 || K < 32 || K % 32 != 0) return false;
+  if ((lda % 8) || (ldb % 8)) return false;
+  const void* ptrs[4] = {A.hi, A.lo, B.hi, B.lo};
+  for (int i = 0; i < 4; ++i)
+    if (((uintptr_t)ptrs[i] & 15) || (mode == RP_BF16X3 && !ptrs[i] && i % 2 == 1)) return false;
+  if (mode == RP_F32) {
+    if (out == RP_OUT_F32)
+      launch_rp_tag<RP_F32, RP_OUT_F32>(tag, A, lda, B, ldb, C, Clo, om, M, N, K, maxbits, s);
+    else if (out == RP_OUT_F64)
+      launch_rp_tag<RP_F32, RP_OUT_F64>(tag, A, lda, B, ldb, C, Clo, om, M, N, K, maxbits, s);
+    else
+      return false;
+  } else {
+    if (out == RP_OUT_SPLIT)
+      launch_rp_tag<RP_BF16X3, RP_OUT_SPLIT>(tag, A, lda, B, ldb, C, Clo, om, M, N, K, maxbits, s);
+    else if (out == RP_OUT_F64)
+      launch_rp_tag<RP_BF16X3, RP_OUT_F64>(tag, A, lda, B, ldb, C, Clo, om, M, N, K, maxbits, s);
+    else if (out == RP_OUT_F32)
+      launch_rp_tag<RP_BF16X3, RP_OUT_F32>(tag, A, lda, B, ldb, C, Clo, om, M, N, K, maxbits, s);
+    else
+      return false;
+  }
+  return true;
+}
+
+}  // namespace hotrg

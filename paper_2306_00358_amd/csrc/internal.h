@@ -59,12 +59,41 @@ bool gemm_f64_lds(const double* A, long long lda, const double* B, long long ldb
                   double* C, const OutMap& om, int M, int N, int K, unsigned long long* maxbits,
                   hipStream_t s, int tag, int variant);
 
-// Single-precision variants (FP32 MFMA; split-BF16 with three products).
-// Inputs are float; output is written as float or, when Cd is non-null,
-// as double.
-void gemm_f32(const float* A, long long lda, const float* B, long long ldb, int blayout,
-              float* C, double* Cd, const OutMap& om, int M, int N, int K,
-              unsigned long long* maxbits, bool bf16x3, hipStream_t s);
+// ---- reduced-precision contractions (gemm_rp.hip) ----
+enum RpMode { RP_F32 = 0, RP_BF16X3 = 1 };
+enum RpOut { RP_OUT_F32 = 0, RP_OUT_SPLIT = 1, RP_OUT_F64 = 2 };
+// An operand: one float array (RP_F32) or bf16 arrays hi and lo (RP_BF16X3).
+struct RpOperand {
+  const void* hi;
+  const void* lo;
+};
+// C[map(m,n)] = sum_k A[m][k] B[n][k]; rows of lda / ldb elements (multiples
+// of 8, zero past the true K); K a multiple of 32.  Output as float, split
+// bf16 (C = hi, Clo = lo) or double.  Returns false if a requirement fails.
+bool gemm_rp(int mode, const RpOperand& A, long long lda, const RpOperand& B, long long ldb,
+             int out, void* C, void* Clo, const OutMap& om, int M, int N, int K,
+             unsigned long long* maxbits, hipStream_t s, int tag);
+inline long long pad32(long long k) { return (k + 31) / 32 * 32; }
+
+// Reduced-precision operands of a step from the coarse tensor `src` (f64 or
+// f32, legs optionally transposed, divided by the max read from maxbits).
+// Each output is an RpOperand written in `mode`; rows are zero-padded to the
+// lengths given (multiples of 32):
+//   Tn   natural float tensor (dx,dy,dx,dy)               (also the state)
+//   OT   rows (l,u), K (r,d), row length ldP                (environment half)
+//   OX   rows (l,d), K (u,r), row length ldP                (environment half)
+//   OC1  rows (j,d,c), K b, row length ldx                  (first contraction)
+//   OC2  rows (l,e), K (a,c) of T[a,c,e,l], row length ldP  (O(D^7) contraction)
+struct RpOps {
+  void* hi[4];
+  void* lo[4];
+};
+void launch_prep_rp(const void* src, bool src_f32, bool rotate, int dx, int dy,
+                    const unsigned long long* maxbits, float* Tn, int mode, const RpOps& ops,
+                    long long ldP, long long ldx, hipStream_t s);
+// U1 rows (i,a), K b (row length ldx); U3 rows k, K (d,e) = U[e,d,k] (row length ldn)
+void launch_layout_u_rp(const double* Ucan, int dx, int dn, int mode, void* u1hi, void* u1lo,
+                        void* u3hi, void* u3lo, long long ldx, long long ldn, hipStream_t s);
 
 // ---- small kernels (kernels.hip) ----
 void launch_maxabs(const void* x, long long n, bool is_f32, unsigned long long* maxbits, hipStream_t s);
@@ -96,5 +125,6 @@ void launch_norm(const unsigned long long* maxbits, const void* Tt, bool f32, in
 void launch_finish(const void* Tn, bool f32, int dx, int dy, double weight, const double* acc,
                    double* out, hipStream_t s);
 void launch_f64_to_f32(const double* x, float* y, long long n, hipStream_t s);
+void launch_f32_to_f64(const float* x, double* y, long long n, hipStream_t s);
 
 }  // namespace hotrg

@@ -250,10 +250,88 @@ void launch_finish(const void* Tn, bool f32, int dx, int dy, double weight, cons
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, Tn, f32, dx, dy, weight, acc, out);
 }
 
+// ----------------------------------------------- reduced-precision operands --
+__device__ __forceinline__ void st_rp(void* hi, void* lo, long long i, float v, int mode) {
+  if (mode == RP_F32) {
+    ((float*)hi)[i] = v;
+  } else {
+    const __bf16 h = (__bf16)v;
+    ((__bf16*)hi)[i] = h;
+    ((__bf16*)lo)[i] = (__bf16)(v - (float)h);
+  }
+}
+
+__global__ void k_prep_rp(const void* src, bool src_f32, bool rotate, int dx, int dy,
+                          const unsigned long long* maxbits, float* Tn, int mode, RpOps ops,
+                          long long ldP, long long ldx) {
+  const double inv = 1.0 / __longlong_as_double((long long)*maxbits);
+  const long long total = (long long)dx * dy * dx * dy;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    long long q = e;
+    const int d = (int)(q % dy); q /= dy;
+    const int r = (int)(q % dx); q /= dx;
+    const int u = (int)(q % dy); q /= dy;
+    const int l = (int)q;
+    const long long si = rotate ? (((long long)u * dx + l) * dy + d) * dx + r : e;
+    const float v = (float)(ld_any(src, si, src_f32) * inv);
+    Tn[e] = v;
+    // OT rows (l,u), K (r,d)
+    st_rp(ops.hi[0], ops.lo[0], ((long long)l * dy + u) * ldP + (long long)r * dy + d, v, mode);
+    // OX rows (l,d), K (u,r)
+    st_rp(ops.hi[1], ops.lo[1], ((long long)l * dy + d) * ldP + (long long)u * dx + r, v, mode);
+    // OC1: element (row (j,d,c), k b) = T[b,j,d,c]: here b=l, j=u, d=r, c=d
+    st_rp(ops.hi[2], ops.lo[2], (((long long)u * dx + r) * dy + d) * ldx + l, v, mode);
+    // OC2: element (row (l,e), k (a,c)) = T[a,c,e,l]: a=l, c=u, e=r, l=d
+    st_rp(ops.hi[3], ops.lo[3], ((long long)d * dx + r) * ldP + (long long)l * dy + u, v, mode);
+  }
+}
+
+void launch_prep_rp(const void* src, bool src_f32, bool rotate, int dx, int dy,
+                    const unsigned long long* maxbits, float* Tn, int mode, const RpOps& ops,
+                    long long ldP, long long ldx, hipStream_t s) {
+  const long long total = (long long)dx * dy * dx * dy;
+  hipLaunchKernelGGL(k_prep_rp, dim3(nblocks(total, 256)), dim3(256), 0, s, src, src_f32, rotate,
+                     dx, dy, maxbits, Tn, mode, ops, ldP, ldx);
+}
+
+__global__ void k_layout_u_rp(const double* Ucan, int dx, int dn, int mode, void* u1hi,
+                              void* u1lo, void* u3hi, void* u3lo, long long ldx, long long ldn) {
+  const long long total = (long long)dx * dx * dn;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(e % dn);
+    const int ab = (int)(e / dn);
+    const int a = ab / dx, b = ab % dx;
+    const float v = (float)Ucan[e];
+    // U1 rows (i,a), k = b
+    st_rp(u1hi, u1lo, ((long long)i * dx + a) * ldx + b, v, mode);
+    // U3 rows k = i, K (d,e) with U[e,d,k]: (a,b) plays (e,d) -> column d*dx + e = b*dx + a
+    st_rp(u3hi, u3lo, (long long)i * ldn + (long long)b * dx + a, v, mode);
+  }
+}
+
+void launch_layout_u_rp(const double* Ucan, int dx, int dn, int mode, void* u1hi, void* u1lo,
+                        void* u3hi, void* u3lo, long long ldx, long long ldn, hipStream_t s) {
+  const long long total = (long long)dx * dx * dn;
+  hipLaunchKernelGGL(k_layout_u_rp, dim3(nblocks(total, 256)), dim3(256), 0, s, Ucan, dx, dn, mode,
+                     u1hi, u1lo, u3hi, u3lo, ldx, ldn);
+}
+
 __global__ void k_f64_to_f32(const double* x, float* y, long long n) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
     y[i] = (float)x[i];
+}
+
+__global__ void k_f32_to_f64(const float* x, double* y, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    y[i] = (double)x[i];
+}
+
+void launch_f32_to_f64(const float* x, double* y, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(k_f32_to_f64, dim3(nblocks(n, 256)), dim3(256), 0, s, x, y, n);
 }
 
 void launch_f64_to_f32(const double* x, float* y, long long n, hipStream_t s) {
