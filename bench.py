@@ -8,11 +8,16 @@ built on the host inside the call.  `value` is directional coarse-graining
 steps per second over the timed runs.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec fp64|fp32|bf16x3]
-                    [--no-cpu-baseline]
+                    [--no-cpu-baseline] [--no-compare] [--kernel-probe]
 
-Prints one JSON line.  The dominant kernel is the D^7 contraction (C2);
-its average duration over the steady-state steps of the timed runs comes
-from HIP events recorded on the library's stream around each phase.
+Prints one JSON line.  The headline (`value`) uses --prec contractions
+(FP64 by default, the precision of the paper's runs); `mixed_vs_fp64`
+repeats the workload with FP32 and split-BF16 x3 contractions (the FP64
+eigensolver and log-norm accumulation are unchanged) and states each
+result's ln Z/N error against the stored FP64 oracle.  The dominant kernel
+is the D^7 contraction (C2); its average duration over the steady-state
+steps of the timed runs comes from HIP events recorded on the library's
+stream around each phase.
 """
 
 import argparse
@@ -46,6 +51,8 @@ def parse():
     ap.add_argument("--d-cut", type=int, default=64)
     ap.add_argument("--n-steps", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the FP32 / split-BF16 runs of the same workload")
     ap.add_argument("--kernel-probe", action="store_true",
                     help="run one coarse contraction at the benchmark shape and a 1 GiB "
                          "calibration copy (for hardware-counter runs), then exit")
@@ -131,42 +138,57 @@ def main():
     torch.cuda.set_device(dev)
     ctx = Context(0)
     params = model_params("ising", beta=BETA_C)
-    opts = make_opts(args.d_cut, args.n_steps, prec=args.prec, spec_len=0)
     sched = dims_schedule(2, args.d_cut, args.n_steps)
     flops_run = sum(step_flops(*d)["total"] for d in sched)
-
-    for _ in range(args.warmup):
-        hotrg_run(ctx, params, opts)
-    ctx.timings()  # discard
-    ctx.enable_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    results = [hotrg_run(ctx, params, opts) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ctx.enable_timing(False)
-    recs = ctx.timings()
-
     steady = (args.d_cut, args.d_cut, args.d_cut)
-    c2 = [r["ms"] for r in recs if r["phase"] == "c2" and (r["dx"], r["dy"], r["d_new"]) == steady]
-    phase_ms = {}
-    for r in recs:
-        phase_ms[r["phase"]] = phase_ms.get(r["phase"], 0.0) + r["ms"] / args.steps
-    c2_ms = sum(c2) / len(c2) if c2 else float("nan")
-    c2_flop = step_flops(*steady)["c2"]
-    achieved = c2_flop / (c2_ms * 1e-3) / 1e12
-    peak = PEAKS[args.prec]
+    golden = os.path.join(ROOT, "tests", "golden", "ising_d64.json")
+    ref = None
+    if args.d_cut == 64 and args.n_steps <= 40 and os.path.exists(golden):
+        with open(golden) as f:
+            ref = json.load(f)["runs"][0]["steps"][args.n_steps - 1]["lnz_torus"]
 
-    lnz = results[-1]["lnz_per_site"]
-    n_dir = args.n_steps * args.steps
+    def measure(prec):
+        opts = make_opts(args.d_cut, args.n_steps, prec=prec, spec_len=0)
+        for _ in range(args.warmup):
+            hotrg_run(ctx, params, opts)
+        ctx.timings()  # discard
+        ctx.enable_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        results = [hotrg_run(ctx, params, opts) for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        ctx.enable_timing(False)
+        recs = ctx.timings()
+        c2 = [r["ms"] for r in recs
+              if r["phase"] == "c2" and (r["dx"], r["dy"], r["d_new"]) == steady]
+        phase_ms = {}
+        for r in recs:
+            phase_ms[r["phase"]] = phase_ms.get(r["phase"], 0.0) + r["ms"] / args.steps
+        c2_ms = sum(c2) / len(c2) if c2 else float("nan")
+        achieved = step_flops(*steady)["c2"] / (c2_ms * 1e-3) / 1e12
+        lnz = results[-1]["lnz_per_site"]
+        return {
+            "steps_per_s": args.n_steps * args.steps / elapsed,
+            "ms_per_run": elapsed / args.steps * 1e3,
+            "tflops": flops_run * args.steps / elapsed / 1e12,
+            "lnz_per_site": lnz,
+            "rel_err_vs_fp64_oracle": abs(lnz - ref) / abs(ref) if ref is not None else None,
+            "rel_err_vs_onsager": abs(lnz - ONSAGER_TC) / ONSAGER_TC,
+            "phase_ms_per_run": phase_ms,
+            "c2_ms": c2_ms, "c2_launches": len(c2), "c2_tflops": achieved,
+        }
+
+    head = measure(args.prec)
+    peak = PEAKS[args.prec]
     out = {
         "metric": METRIC,
-        "value": n_dir / elapsed,
+        "value": head["steps_per_s"],
         "unit": "steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
+        "ms_per_step": head["ms_per_run"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -176,21 +198,32 @@ def main():
                                % (args.d_cut, args.n_steps, args.prec),
                    "d_cut": args.d_cut, "n_steps": args.n_steps, "prec": args.prec,
                    "beta": BETA_C},
-        "tflops": flops_run * args.steps / elapsed / 1e12,
-        "lnz_per_site": lnz,
-        "rel_err_vs_onsager": abs(lnz - ONSAGER_TC) / ONSAGER_TC,
-        "phase_ms_per_run": phase_ms,
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": TRAFFIC.get((args.prec, args.d_cut)),
+        "tflops": head["tflops"],
+        "lnz_per_site": head["lnz_per_site"],
+        "rel_err_vs_onsager": head["rel_err_vs_onsager"],
+        "rel_err_vs_oracle": head["rel_err_vs_fp64_oracle"],
+        "phase_ms_per_run": head["phase_ms_per_run"],
+        "roofline": {"bound": "mfma", "achieved": head["c2_tflops"], "peak": peak,
+                     "unit": "TFLOP/s", "frac": head["c2_tflops"] / peak,
+                     "traffic": TRAFFIC.get((args.prec, args.d_cut)),
                      "kernel": "C2 GEMM %dx%dx%d" % (args.d_cut**3, args.d_cut**2, args.d_cut**2),
-                     "kernel_ms": c2_ms, "launches": len(c2)},
+                     "kernel_ms": head["c2_ms"], "launches": head["c2_launches"]},
     }
-    golden = os.path.join(ROOT, "tests", "golden", "ising_d64.json")
-    if args.d_cut == 64 and args.n_steps <= 40 and os.path.exists(golden):
-        with open(golden) as f:
-            rec = json.load(f)["runs"][0]
-        ref = rec["steps"][args.n_steps - 1]["lnz_torus"]
-        out["rel_err_vs_oracle"] = abs(lnz - ref) / abs(ref)
+    if not args.no_compare:
+        # the same workload with reduced-precision contractions (eigensolver
+        # and log-norm stay FP64)
+        mixed = {}
+        for prec in ("fp32", "bf16x3"):
+            if prec == args.prec:
+                continue
+            m = measure(prec)
+            m["speedup_vs_" + args.prec] = m["steps_per_s"] / head["steps_per_s"]
+            m["c2_frac_of_peak"] = m["c2_tflops"] / PEAKS[prec]
+            if prec == "bf16x3":
+                # three bf16 products are issued per multiply-add
+                m["c2_issued_frac_of_peak"] = 3 * m["c2_tflops"] / PEAKS[prec]
+            mixed[prec] = m
+        out["mixed_vs_" + args.prec] = mixed
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.d_cut)
     print(json.dumps(out), flush=True)
