@@ -108,7 +108,9 @@ typedef struct {
   hotrg_step_info* steps;  /* caller-owned array of n_steps entries, or NULL */
   double* spectra;         /* caller-owned [n_steps][spec_len] lambda/lambda_1
                               descending (zero past dx*dx), or NULL */
-  double seconds;          /* wall time of the call */
+  double seconds;          /* wall time of the run itself */
+  double t_submit, t_start, t_end; /* submitted requests: host times in seconds
+                                      since the context was created */
 } hotrg_result;
 
 typedef struct hotrg_ctx hotrg_ctx;
@@ -153,6 +155,45 @@ void hotrg_state_free(hotrg_ctx* ctx, hotrg_state* st);
  * end.  result->steps / result->spectra are filled when non-NULL. */
 hotrg_status hotrg_run(hotrg_ctx* ctx, const hotrg_model_params* params, const hotrg_opts* opts,
                        hotrg_result* result);
+
+/* ---- many problems: batch and serving loop ------------------------------
+ * The context runs submitted problems on a pool of workers, each with its
+ * own HIP stream and device workspace, so problems overlap on the GPU.  A
+ * queued problem is admitted when a worker is free and its estimated
+ * device footprint fits the HBM budget (the context's hbm_budget, or 90% of
+ * the free device memory when that is 0) next to the running ones; a problem
+ * that can never fit fails with HOTRG_ERR_OOM.  A problem's result does not
+ * depend on what runs beside it (same kernels, same order).
+ * submit/poll/wait/cancel are thread-safe. */
+
+/* Worker count (default 4); takes effect before the first submit or batch. */
+hotrg_status hotrg_ctx_set_workers(hotrg_ctx* ctx, int n_workers);
+
+/* Queue one problem.  `result` is caller-owned and must stay valid (with its
+ * steps/spectra arrays, if set) until the problem completes or is cancelled;
+ * the raw tensor of HOTRG_RAW is copied during the call. */
+hotrg_status hotrg_submit(hotrg_ctx* ctx, const hotrg_model_params* params, const hotrg_opts* opts,
+                          hotrg_result* result, uint64_t* ticket);
+/* HOTRG_ERR_NOT_READY while queued or running; afterwards the problem's own
+ * status (HOTRG_OK, an error, or HOTRG_ERR_CANCELLED).  A finished ticket
+ * stays valid until the context is destroyed. */
+hotrg_status hotrg_poll(hotrg_ctx* ctx, uint64_t ticket);
+/* Wait up to timeout_s seconds (< 0: no limit); returns as hotrg_poll. */
+hotrg_status hotrg_wait(hotrg_ctx* ctx, uint64_t ticket, double timeout_s);
+/* Cancel a queued problem, or stop a running one at its next step boundary. */
+hotrg_status hotrg_cancel(hotrg_ctx* ctx, uint64_t ticket);
+/* Estimated peak device bytes of one problem (the admission footprint). */
+hotrg_status hotrg_footprint(const hotrg_model_params* params, const hotrg_opts* opts,
+                             size_t* bytes);
+/* Run n problems on the worker pool and wait for all; `statuses` (may be
+ * NULL) receives each problem's status; returns the first failure or OK. */
+hotrg_status hotrg_run_batch(hotrg_ctx* ctx, int n, const hotrg_model_params* params,
+                             const hotrg_opts* opts, hotrg_result* results,
+                             hotrg_status* statuses);
+/* Serving counters: requests admitted, queue passes where the oldest queued
+ * request did not fit, peak bytes reserved by running requests. */
+hotrg_status hotrg_ctx_sched_stats(hotrg_ctx* ctx, uint64_t* admitted, uint64_t* stalls,
+                                   size_t* peak_reserved);
 
 /* ---- per-phase timing (HIP events on the context's stream) -------------
  * When enabled, every phase of every step is bracketed by HIP events;

@@ -10,6 +10,7 @@ arguments; see ``_lib`` for the calls.
 from ._lib import (  # noqa: F401
     EXPORTS, HOTRG_BF16X3, HOTRG_FP32, HOTRG_FP64, HOTRG_ISING, HOTRG_POTTS, HOTRG_RAW,
     HOTRG_TRUNC_MULTIPLET, HOTRG_TRUNC_PLAIN, HOTRG_XY, LIB_PATH, Context, HotrgError, State,
-    hotrg_coarse, hotrg_environment, hotrg_run, lib, make_opts, model_params,
+    Ticket, hotrg_coarse, hotrg_environment, hotrg_footprint, hotrg_run, hotrg_run_batch, lib,
+    make_opts, model_params,
 )
 from .flops import step_flops, run_flops, dims_schedule  # noqa: F401

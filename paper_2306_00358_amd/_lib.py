@@ -25,6 +25,8 @@ EXPORTS = [
     "hotrg_ctx_create", "hotrg_ctx_destroy", "hotrg_last_error", "hotrg_ctx_bytes_in_use",
     "hotrg_init_tensor", "hotrg_step", "hotrg_finish", "hotrg_state_export", "hotrg_state_free",
     "hotrg_run", "hotrg_environment", "hotrg_coarse", "hotrg_ctx_enable_timing", "hotrg_ctx_timings",
+    "hotrg_ctx_set_workers", "hotrg_submit", "hotrg_poll", "hotrg_wait", "hotrg_cancel",
+    "hotrg_footprint", "hotrg_run_batch", "hotrg_ctx_sched_stats",
 ]
 
 PHASES = ["env", "eigh", "proj", "c1", "c2", "c3", "norm"]
@@ -62,7 +64,8 @@ class PhaseTime(ctypes.Structure):
 
 class Result(ctypes.Structure):
     _fields_ = [("lnz_per_site", c_double), ("n_steps", c_int), ("steps", POINTER(StepInfo)),
-                ("spectra", POINTER(c_double)), ("seconds", c_double)]
+                ("spectra", POINTER(c_double)), ("seconds", c_double), ("t_submit", c_double),
+                ("t_start", c_double), ("t_end", c_double)]
 
 
 _lib = None
@@ -94,6 +97,17 @@ def lib():
     L.hotrg_environment.argtypes = [vp, c_int, vp, c_int, c_int, vp]
     L.hotrg_coarse.argtypes = [vp, c_int, vp, vp, c_int, c_int, c_int, vp, vp]
     L.hotrg_ctx_enable_timing.argtypes = [vp, c_int]
+    L.hotrg_ctx_set_workers.argtypes = [vp, c_int]
+    L.hotrg_submit.argtypes = [vp, POINTER(ModelParams), POINTER(Opts), POINTER(Result),
+                               POINTER(ctypes.c_uint64)]
+    L.hotrg_poll.argtypes = [vp, ctypes.c_uint64]
+    L.hotrg_wait.argtypes = [vp, ctypes.c_uint64, c_double]
+    L.hotrg_cancel.argtypes = [vp, ctypes.c_uint64]
+    L.hotrg_footprint.argtypes = [POINTER(ModelParams), POINTER(Opts), POINTER(c_size_t)]
+    L.hotrg_run_batch.argtypes = [vp, c_int, POINTER(ModelParams), POINTER(Opts), POINTER(Result),
+                                  POINTER(c_int)]
+    L.hotrg_ctx_sched_stats.argtypes = [vp, POINTER(ctypes.c_uint64), POINTER(ctypes.c_uint64),
+                                        POINTER(c_size_t)]
     L.hotrg_ctx_timings.argtypes = [vp, POINTER(PhaseTime), c_int]
     for name in EXPORTS:
         if name not in ("hotrg_ctx_destroy", "hotrg_state_free", "hotrg_last_error",
@@ -166,6 +180,14 @@ class Context:
 
     def bytes_in_use(self):
         return lib().hotrg_ctx_bytes_in_use(self.ptr)
+
+    def set_workers(self, n):
+        _check(lib().hotrg_ctx_set_workers(self.ptr, int(n)))
+
+    def sched_stats(self):
+        a, st, pk = ctypes.c_uint64(), ctypes.c_uint64(), c_size_t()
+        _check(lib().hotrg_ctx_sched_stats(self.ptr, byref(a), byref(st), byref(pk)))
+        return {"admitted": a.value, "stalls": st.value, "peak_reserved": pk.value}
 
     def enable_timing(self, on=True):
         _check(lib().hotrg_ctx_enable_timing(self.ptr, 1 if on else 0))
@@ -258,3 +280,78 @@ def hotrg_coarse(ctx, T, U, Tt, max_abs=None, prec="fp64"):
     _check(lib().hotrg_coarse(ctx.ptr, _prec(prec), c_void_p(T.data_ptr()), c_void_p(U.data_ptr()),
                               dx, dy, dn, c_void_p(Tt.data_ptr()),
                               c_void_p(max_abs.data_ptr()) if max_abs is not None else None))
+
+
+def _result_dict(r, infos, spec, K, spec_len):
+    return {"lnz_per_site": r.lnz_per_site, "n_steps": r.n_steps,
+            "steps": [infos[i].as_dict() for i in range(K)] if infos is not None else [],
+            "spectra": spec[:K, :spec_len] if spec is not None else None,
+            "seconds": r.seconds, "t_submit": r.t_submit, "t_start": r.t_start, "t_end": r.t_end}
+
+
+def hotrg_footprint(params, opts):
+    b = c_size_t()
+    _check(lib().hotrg_footprint(byref(params), byref(opts), byref(b)))
+    return b.value
+
+
+def hotrg_run_batch(ctx, params_list, opts_list, with_steps=False):
+    """Run problems on the context's worker pool; returns (list of result
+    dicts or None for failed problems, list of statuses)."""
+    n = len(params_list)
+    P = (ModelParams * n)(*params_list)
+    O = (Opts * n)(*opts_list)
+    R = (Result * n)()
+    keep = []
+    for i, o in enumerate(opts_list):
+        if with_steps:
+            infos = (StepInfo * max(o.n_steps, 1))()
+            spec = np.zeros((max(o.n_steps, 1), max(o.spec_len, 1)))
+            R[i].steps = ctypes.cast(infos, POINTER(StepInfo))
+            R[i].spectra = spec.ctypes.data_as(POINTER(c_double)) if o.spec_len else None
+            keep.append((infos, spec))
+        else:
+            keep.append((None, None))
+    S = (c_int * n)()
+    lib().hotrg_run_batch(ctx.ptr, n, P, O, R, S)
+    out = []
+    for i in range(n):
+        if S[i] != HOTRG_OK:
+            out.append(None)
+        else:
+            infos, spec = keep[i]
+            out.append(_result_dict(R[i], infos, spec, opts_list[i].n_steps, opts_list[i].spec_len))
+    return out, [int(x) for x in S]
+
+
+class Ticket:
+    """A submitted problem: the result buffers live here until it completes."""
+
+    def __init__(self, ctx, params, opts, with_steps=False):
+        self.ctx, self.params, self.opts = ctx, params, opts
+        self.result = Result()
+        self.infos = self.spec = None
+        if with_steps:
+            self.infos = (StepInfo * max(opts.n_steps, 1))()
+            self.spec = np.zeros((max(opts.n_steps, 1), max(opts.spec_len, 1)))
+            self.result.steps = ctypes.cast(self.infos, POINTER(StepInfo))
+            self.result.spectra = (self.spec.ctypes.data_as(POINTER(c_double))
+                                   if opts.spec_len else None)
+        self.id = ctypes.c_uint64()
+        _check(lib().hotrg_submit(ctx.ptr, byref(params), byref(opts), byref(self.result),
+                                  byref(self.id)))
+
+    def poll(self):
+        return lib().hotrg_poll(self.ctx.ptr, self.id)
+
+    def wait(self, timeout=-1.0):
+        return lib().hotrg_wait(self.ctx.ptr, self.id, float(timeout))
+
+    def cancel(self):
+        _check(lib().hotrg_cancel(self.ctx.ptr, self.id))
+
+    def value(self):
+        st = self.wait()
+        if st != HOTRG_OK:
+            raise HotrgError(st, lib().hotrg_last_error().decode())
+        return _result_dict(self.result, self.infos, self.spec, self.opts.n_steps, self.opts.spec_len)

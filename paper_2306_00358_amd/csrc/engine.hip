@@ -14,6 +14,7 @@
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -71,6 +72,10 @@ struct hotrg_ctx {
   // 32 primitive max (u64), 40 trace(M) (double), 48 iterative solver info (int)
   int last_eig_iters = 0;      // sweeps of the last iterative solve (0: dense solver)
   double last_eig_resid = 0.0;
+  // many-problem scheduler (sched.cpp), created on first use
+  void* sched = nullptr;
+  int n_workers = 4;
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
   // per-phase timing
   bool timing = false;
   struct Mark {
@@ -634,6 +639,70 @@ hotrg_status guard(F&& f) {
 
 }  // namespace
 
+namespace hotrg {
+
+hotrg_status run_problem(hotrg_ctx* c, const hotrg_model_params* params, const hotrg_opts* o,
+                         hotrg_result* res, const std::atomic<bool>* cancel) {
+  hotrg_state* st = nullptr;
+  hotrg_status s = guard([&] {
+    if (!c || !res) fail(HOTRG_ERR_INVALID, "ctx/result is NULL");
+    check_opts(o);
+    HIPCHK(hipSetDevice(c->device));
+    auto t0 = std::chrono::steady_clock::now();
+    int dx = 0, dy = 0;
+    std::vector<double> T0 = build_tensor(params, &dx, &dy);
+    st = new_state(c, T0, dx, dy, o->prec);
+    std::vector<int> dxs, dys, dns;
+    for (int k = 0; k < o->n_steps; ++k) {
+      if (cancel && cancel->load()) fail(HOTRG_ERR_CANCELLED, "cancelled");
+      dxs.push_back(st->dx);
+      dys.push_back(st->dy);
+      do_step(c, st, o);
+      dns.push_back(st->dy);
+    }
+    double lnz = 0;
+    hotrg_status fs = hotrg_finish(c, st, &lnz);
+    if (fs != HOTRG_OK) fail(fs, g_err);
+    if (res->steps || res->spectra) {
+      fetch_info(c, st, 0, o->n_steps, nullptr, res->steps, res->spectra);
+      if (res->steps)
+        for (int k = 0; k < o->n_steps; ++k) {
+          res->steps[k].dx = dxs[k];
+          res->steps[k].dy = dys[k];
+          res->steps[k].d_new = dns[k];
+        }
+    }
+    res->lnz_per_site = lnz;
+    res->n_steps = o->n_steps;
+    res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  });
+  if (st) hotrg_state_free(c, st);
+  return s;
+}
+
+void ctx_trim(hotrg_ctx* c) {
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  Buf* bufs[] = {&c->A1, &c->A2, &c->M, &c->W, &c->E, &c->Ucan, &c->U1, &c->U3,
+                 &c->X1, &c->X2, &c->Tt, &c->EW, &c->Xr};
+  for (Buf* b : bufs) ctx_free(c, *b);
+  for (Buf* arr : {c->RA1, c->RA2, c->RX1, c->RX2, c->RU1, c->RU3})
+    for (int h = 0; h < 2; ++h) ctx_free(c, arr[h]);
+}
+
+double ctx_seconds(const hotrg_ctx* c) {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now() - c->t0).count();
+}
+int ctx_device(const hotrg_ctx* c) { return c->device; }
+size_t ctx_budget(const hotrg_ctx* c) { return c->budget; }
+int& ctx_workers(hotrg_ctx* c) { return c->n_workers; }
+void*& ctx_sched(hotrg_ctx* c) { return c->sched; }
+const char* last_error_text() { return g_err.c_str(); }
+void set_last_error(const char* m) { g_err = m; }
+
+}  // namespace hotrg
+
+
 extern "C" {
 
 const char* hotrg_last_error(void) { return g_err.c_str(); }
@@ -670,6 +739,7 @@ hotrg_status hotrg_ctx_create(int device, void* hip_stream, size_t hbm_budget, h
 
 void hotrg_ctx_destroy(hotrg_ctx* c) {
   if (!c) return;
+  hotrg::sched_shutdown(c);
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
   Buf* bufs[] = {&c->A1, &c->A2, &c->M, &c->W, &c->E, &c->Ucan, &c->U1, &c->U3,
@@ -790,40 +860,7 @@ void hotrg_state_free(hotrg_ctx* c, hotrg_state* st) {
 
 hotrg_status hotrg_run(hotrg_ctx* c, const hotrg_model_params* params, const hotrg_opts* o,
                        hotrg_result* res) {
-  hotrg_state* st = nullptr;
-  hotrg_status s = guard([&] {
-    if (!c || !res) fail(HOTRG_ERR_INVALID, "ctx/result is NULL");
-    check_opts(o);
-    HIPCHK(hipSetDevice(c->device));
-    auto t0 = std::chrono::steady_clock::now();
-    int dx = 0, dy = 0;
-    std::vector<double> T0 = build_tensor(params, &dx, &dy);
-    st = new_state(c, T0, dx, dy, o->prec);
-    std::vector<int> dxs, dys, dns;
-    for (int k = 0; k < o->n_steps; ++k) {
-      dxs.push_back(st->dx);
-      dys.push_back(st->dy);
-      do_step(c, st, o);
-      dns.push_back(st->dy);
-    }
-    double lnz = 0;
-    hotrg_status fs = hotrg_finish(c, st, &lnz);
-    if (fs != HOTRG_OK) fail(fs, g_err);
-    if (res->steps || res->spectra) {
-      fetch_info(c, st, 0, o->n_steps, nullptr, res->steps, res->spectra);
-      if (res->steps)
-        for (int k = 0; k < o->n_steps; ++k) {
-          res->steps[k].dx = dxs[k];
-          res->steps[k].dy = dys[k];
-          res->steps[k].d_new = dns[k];
-        }
-    }
-    res->lnz_per_site = lnz;
-    res->n_steps = o->n_steps;
-    res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  });
-  if (st) hotrg_state_free(c, st);
-  return s;
+  return hotrg::run_problem(c, params, o, res, nullptr);
 }
 
 hotrg_status hotrg_ctx_enable_timing(hotrg_ctx* c, int on) {

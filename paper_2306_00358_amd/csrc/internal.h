@@ -6,6 +6,10 @@
 #include <rocblas/rocblas.h>
 #include <stdint.h>
 
+#include <atomic>
+
+#include "../../include/hotrg.h"
+
 namespace hotrg {
 
 // Where a GEMM output element (m, n) is stored.  The row index is read as
@@ -126,5 +130,19 @@ void launch_finish(const void* Tn, bool f32, int dx, int dy, double weight, cons
                    double* out, hipStream_t s);
 void launch_f64_to_f32(const double* x, float* y, long long n, hipStream_t s);
 void launch_f32_to_f64(const float* x, double* y, long long n, hipStream_t s);
+
+// ---- engine hooks used by the scheduler (sched.cpp) ----
+// hotrg_run with a cancellation flag checked between steps.
+hotrg_status run_problem(hotrg_ctx* c, const hotrg_model_params* params, const hotrg_opts* o,
+                         hotrg_result* res, const std::atomic<bool>* cancel);
+void ctx_trim(hotrg_ctx* c);  // release the step workspace
+double ctx_seconds(const hotrg_ctx* c);
+int ctx_device(const hotrg_ctx* c);
+size_t ctx_budget(const hotrg_ctx* c);
+int& ctx_workers(hotrg_ctx* c);
+void*& ctx_sched(hotrg_ctx* c);
+void sched_shutdown(hotrg_ctx* c);
+const char* last_error_text();
+void set_last_error(const char* m);
 
 }  // namespace hotrg

@@ -68,3 +68,16 @@ def test_flop_model_matches_oracle_bookkeeping():
         for d in flops.dims_schedule(d0, dc, K):
             # the oracle counts each Gram half as a full square product too
             assert flops.step_flops(*d)["total"] == hotrg.step_flops(*d)
+
+
+def test_footprint_host_estimate():
+    # pure host arithmetic on the dimension schedule (no device call)
+    from paper_2306_00358_amd import hotrg_footprint, make_opts, model_params
+
+    p = model_params("ising", beta=0.44)
+    f32 = hotrg_footprint(p, make_opts(32, 30))
+    f64 = hotrg_footprint(p, make_opts(64, 30))
+    assert 0 < f32 < f64
+    # the two D^5 intermediates dominate: 2 * 64^5 * 8 bytes at D = 64
+    assert 2 * 64**5 * 8 < f64 < 4 * 64**5 * 8
+    assert hotrg_footprint(p, make_opts(64, 30, prec="fp32")) < f64
