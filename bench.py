@@ -53,6 +53,13 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the FP32 / split-BF16 runs of the same workload")
+    ap.add_argument("--batch", action="store_true",
+                    help="the 64-problem XY batch workload instead of the single Ising run")
+    ap.add_argument("--serve", type=int, default=0, metavar="N",
+                    help="serve a seeded Poisson stream of N mixed requests instead")
+    ap.add_argument("--no-serve-check", dest="serve_check", action="store_false",
+                    help="skip the FP64 re-run of every served request")
+    ap.add_argument("--workers", type=int, default=4)
     ap.add_argument("--kernel-probe", action="store_true",
                     help="run one coarse contraction at the benchmark shape and a 1 GiB "
                          "calibration copy (for hardware-counter runs), then exit")
@@ -81,6 +88,197 @@ def kernel_probe(args):
         hotrg_coarse(ctx, T, U, Tt)
     torch.cuda.synchronize()
     print(json.dumps({"kernel_probe": {"d": D, "copy_bytes": 8 * n}}), flush=True)
+
+
+def xy_batch_problems(prec):
+    """The XY batch: beta_i = 0.8 + 0.6 i/63 (inclusive grid), n_max = 3 + (i mod 4),
+    D_cut = (24, 32, 40, 48)[(i div 4) mod 4], 25 directional steps,
+    multiplet-safe truncation (tau 1e-6 for reduced-precision contractions)."""
+    from paper_2306_00358_amd import make_opts, model_params
+
+    probs = []
+    for i in range(64):
+        beta = 0.8 + 0.6 * i / 63.0
+        n_max = 3 + (i % 4)
+        d_cut = (24, 32, 40, 48)[(i // 4) % 4]
+        tau = 1e-10 if prec == "fp64" else 1e-6
+        probs.append((model_params("xy", beta=beta, n_max=n_max),
+                      make_opts(d_cut, 25, prec=prec, trunc="multiplet", degen_tol=tau)))
+    return probs
+
+
+def run_batch_bench(args):
+    import torch
+
+    from paper_2306_00358_amd import Context, hotrg_run_batch
+    from paper_2306_00358_amd.flops import dims_schedule, step_flops
+
+    prec = args.prec if args.prec != "fp64" else "fp32"
+    probs = xy_batch_problems(prec)
+    P = [p for p, _ in probs]
+    O = [o for _, o in probs]
+    flops = sum(sum(step_flops(*d)["total"] for d in dims_schedule(2 * p.n_max + 1, o.d_cut, o.n_steps))
+                for p, o in probs)
+    n_dir = sum(o.n_steps for o in O)
+
+    def timed(workers):
+        with Context(0) as ctx:
+            ctx.set_workers(workers)
+            hotrg_run_batch(ctx, P[:workers], O[:workers])  # warm-up: workspaces, kernels
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res, st = hotrg_run_batch(ctx, P, O)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        assert st == [0] * len(P), st
+        return dt, [r["lnz_per_site"] for r in res]
+
+    t_pool, lnz_pool = timed(args.workers)
+    t_seq, lnz_seq = timed(1)
+    same = all(a == b for a, b in zip(lnz_pool, lnz_seq))
+    out = {
+        "metric": METRIC + " [XY batch]",
+        "value": n_dir / t_pool,
+        "unit": "steps/s",
+        "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": t_pool * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": DTYPE[prec], "data": "synthetic",
+        "config": {"workload": "64 XY problems, beta in [0.8,1.4], n_max 3..6, D_cut in "
+                               "{24,32,40,48}, 25 directional steps, %s contractions" % prec,
+                   "workers": args.workers},
+        "tflops": flops / t_pool / 1e12,
+        "sequential_steps_per_s": n_dir / t_seq,
+        "speedup_vs_sequential": t_seq / t_pool,
+        "batch_equals_sequential": same,
+        "lnz_per_site": lnz_pool,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def log(msg):
+    """Progress line on stderr (the JSON result is the only stdout line)."""
+    print(msg, file=sys.stderr, flush=True)
+
+
+def serve_requests(n, seed=0):
+    """The serving mix: Ising (T uniform in [1.5, 3.5]) or XY (beta uniform in
+    [0.6, 1.6], n_max = 4) with probability 1/2 each, D_cut uniform in
+    {16, 32, 48, 64, 80}, 20-40 directional steps, FP32 or split-BF16 x3
+    contractions; generator PCG64 with the given seed."""
+    import numpy as np
+
+    from paper_2306_00358_amd import make_opts, model_params
+
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for _ in range(n):
+        if rng.random() < 0.5:
+            p = model_params("ising", beta=1.0 / rng.uniform(1.5, 3.5))
+            trunc, tau = "plain", 1e-10
+        else:
+            p = model_params("xy", beta=rng.uniform(0.6, 1.6), n_max=4)
+            trunc, tau = "multiplet", 1e-6
+        o = make_opts(int(rng.choice([16, 32, 48, 64, 80])), int(rng.integers(20, 41)),
+                      prec=str(rng.choice(["fp32", "bf16x3"])), trunc=trunc, degen_tol=tau)
+        reqs.append((p, o))
+    return reqs
+
+
+def run_serve_bench(args):
+    import numpy as np
+    import torch
+
+    from paper_2306_00358_amd import Context, Ticket
+    from paper_2306_00358_amd.flops import dims_schedule, step_flops
+
+    reqs = serve_requests(args.serve, seed=0)
+
+    def d0(p):
+        return 2 if p.model == 0 else 2 * p.n_max + 1
+
+    flops = [sum(step_flops(*d)["total"] for d in dims_schedule(d0(p), o.d_cut, o.n_steps))
+             for p, o in reqs]
+    with Context(0) as ctx:
+        ctx.set_workers(args.workers)
+        # closed loop on a prefix: the saturation rate in requests/s
+        n_pre = max(4, min(len(reqs), 2 * args.workers))
+        t0 = time.perf_counter()
+        pre = [Ticket(ctx, p, o) for p, o in reqs[:n_pre]]
+        for i, t in enumerate(pre):
+            t.value()
+            log("closed-loop request %d/%d done" % (i + 1, n_pre))
+        sat = n_pre / (time.perf_counter() - t0)
+        rate = 0.8 * sat
+        arrivals = np.cumsum(np.random.default_rng(1).exponential(1.0 / rate, size=len(reqs)))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tickets = []
+        for (p, o), ta in zip(reqs, arrivals):
+            while time.perf_counter() - t0 < ta:
+                time.sleep(0.0005)
+            tickets.append(Ticket(ctx, p, o))
+            log("request %d/%d submitted at %.2f s" % (len(tickets), len(reqs), ta))
+        vals = []
+        for i, t in enumerate(tickets):
+            vals.append(t.value())
+            log("request %d/%d done, latency %.2f s" % (i + 1, len(reqs),
+                                                       vals[-1]["t_end"] - vals[-1]["t_submit"]))
+        dt = time.perf_counter() - t0
+        stats = ctx.sched_stats()
+        errors = serve_errors(ctx, reqs, vals) if args.serve_check else None
+    lat = np.array([v["t_end"] - v["t_submit"] for v in vals])
+    wait = np.array([v["t_start"] - v["t_submit"] for v in vals])
+    n_dir = sum(o.n_steps for _, o in reqs)
+    out = {
+        "metric": METRIC + " [serving]",
+        "value": n_dir / dt,
+        "unit": "steps/s",
+        "n_gpus": 1, "steps": len(reqs), "warmup": n_pre,
+        "ms_per_step": dt / len(reqs) * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "fp32/bf16x3", "data": "synthetic",
+        "config": {"workload": "seeded Poisson stream of %d Ising/XY requests, D_cut in "
+                               "{16..80}, 20-40 steps" % len(reqs),
+                   "workers": args.workers, "arrival_rate_per_s": rate,
+                   "saturation_rate_per_s": sat},
+        "tflops": sum(flops) / dt / 1e12,
+        "latency_p50_s": float(np.percentile(lat, 50)),
+        "latency_p99_s": float(np.percentile(lat, 99)),
+        "queue_wait_p50_s": float(np.percentile(wait, 50)),
+        "queue_wait_p99_s": float(np.percentile(wait, 99)),
+        "admission": stats,
+        "fp64_reruns": sum(1 for v, (_, o) in zip(vals, reqs) if v["prec_used"] != o.prec),
+        "lnz_rel_error_vs_fp64": errors,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def serve_errors(ctx, reqs, vals):
+    """ln Z/N of every served result against the same request with FP64
+    contractions (the FP64 path matches the oracle to 1e-12); run after the
+    timed stream.  Summarised per requested precision and model."""
+    import numpy as np
+
+    from paper_2306_00358_amd import HotrgError, Ticket, make_opts
+
+    tickets = [Ticket(ctx, p, make_opts(o.d_cut, o.n_steps, prec="fp64", trunc=o.trunc,
+                                        degen_tol=o.degen_tol)) for p, o in reqs]
+    out = {}
+    for i, ((p, o), v, t) in enumerate(zip(reqs, vals, tickets)):
+        try:
+            r = t.value()
+        except HotrgError as e:
+            log("fp64 check %d/%d failed: %s" % (i + 1, len(reqs), e))
+            continue
+        log("fp64 check %d/%d done" % (i + 1, len(reqs)))
+        key = "%s/%s" % ({0: "fp64", 1: "fp32", 2: "bf16x3"}[o.prec],
+                         {0: "ising", 1: "xy"}.get(p.model, "other"))
+        e = abs(v["lnz_per_site"] - r["lnz_per_site"]) / abs(r["lnz_per_site"])
+        out.setdefault(key, []).append((e, v["prec_used"] != o.prec))
+    return {k: {"n": len(v), "fp64_reruns": sum(f for _, f in v),
+                "max": max(e for e, _ in v), "median": float(np.median([e for e, _ in v]))}
+            for k, v in sorted(out.items())}
 
 
 def cpu_baseline(d_cut):
@@ -133,6 +331,12 @@ def main():
     assert torch.cuda.is_available(), "no GPU"
     if args.kernel_probe:
         kernel_probe(args)
+        return
+    if args.batch:
+        run_batch_bench(args)
+        return
+    if args.serve:
+        run_serve_bench(args)
         return
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)

@@ -111,6 +111,9 @@ typedef struct {
   double seconds;          /* wall time of the run itself */
   double t_submit, t_start, t_end; /* submitted requests: host times in seconds
                                       since the context was created */
+  int prec_used;           /* precision the result was computed with (a
+                              submitted reduced-precision problem that fails
+                              with HOTRG_ERR_NUMERIC is re-run once in FP64) */
 } hotrg_result;
 
 typedef struct hotrg_ctx hotrg_ctx;
@@ -163,7 +166,11 @@ hotrg_status hotrg_run(hotrg_ctx* ctx, const hotrg_model_params* params, const h
  * device footprint fits the HBM budget (the context's hbm_budget, or 90% of
  * the free device memory when that is 0) next to the running ones; a problem
  * that can never fit fails with HOTRG_ERR_OOM.  A problem's result does not
- * depend on what runs beside it (same kernels, same order).
+ * depend on what runs beside it (same kernels, same order).  A problem with
+ * FP32 / split-BF16 contractions that ends with HOTRG_ERR_NUMERIC (e.g. a
+ * non-positive final trace after reduced-precision noise has driven the
+ * flow away) is queued once more with FP64 contractions; prec_used says
+ * which precision produced the result.
  * submit/poll/wait/cancel are thread-safe. */
 
 /* Worker count (default 4); takes effect before the first submit or batch. */

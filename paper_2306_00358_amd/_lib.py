@@ -65,7 +65,7 @@ class PhaseTime(ctypes.Structure):
 class Result(ctypes.Structure):
     _fields_ = [("lnz_per_site", c_double), ("n_steps", c_int), ("steps", POINTER(StepInfo)),
                 ("spectra", POINTER(c_double)), ("seconds", c_double), ("t_submit", c_double),
-                ("t_start", c_double), ("t_end", c_double)]
+                ("t_start", c_double), ("t_end", c_double), ("prec_used", c_int)]
 
 
 _lib = None
@@ -214,7 +214,7 @@ def hotrg_run(ctx, params, opts):
     _check(lib().hotrg_run(ctx.ptr, byref(params), byref(opts), byref(r)))
     return {"lnz_per_site": r.lnz_per_site, "n_steps": r.n_steps,
             "steps": [infos[i].as_dict() for i in range(K)],
-            "spectra": spec[:K, :opts.spec_len], "seconds": r.seconds}
+            "spectra": spec[:K, :opts.spec_len], "seconds": r.seconds, "prec_used": r.prec_used}
 
 
 class State:
@@ -286,7 +286,8 @@ def _result_dict(r, infos, spec, K, spec_len):
     return {"lnz_per_site": r.lnz_per_site, "n_steps": r.n_steps,
             "steps": [infos[i].as_dict() for i in range(K)] if infos is not None else [],
             "spectra": spec[:K, :spec_len] if spec is not None else None,
-            "seconds": r.seconds, "t_submit": r.t_submit, "t_start": r.t_start, "t_end": r.t_end}
+            "seconds": r.seconds, "t_submit": r.t_submit, "t_start": r.t_start, "t_end": r.t_end,
+            "prec_used": r.prec_used}
 
 
 def hotrg_footprint(params, opts):

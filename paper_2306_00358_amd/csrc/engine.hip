@@ -674,6 +674,7 @@ hotrg_status run_problem(hotrg_ctx* c, const hotrg_model_params* params, const h
     }
     res->lnz_per_site = lnz;
     res->n_steps = o->n_steps;
+    res->prec_used = o->prec;
     res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   });
   if (st) hotrg_state_free(c, st);

@@ -54,6 +54,7 @@ struct Request {
   std::string err;
   size_t footprint = 0;
   int skips = 0;
+  bool retried = false;
 };
 
 struct Server {
@@ -65,6 +66,7 @@ struct Server {
   std::condition_variable done_cv;  // a request finished
   std::deque<std::shared_ptr<Request>> queue;
   std::unordered_map<uint64_t, std::shared_ptr<Request>> all;
+  std::vector<size_t> hold;         // bytes held by each idle worker
   size_t budget = 0;
   size_t reserved = 0;
   size_t peak_reserved = 0;
@@ -145,25 +147,35 @@ size_t footprint_of(const hotrg_model_params* p, const hotrg_opts* o) {
 }
 
 // ------------------------------------------------------------------ server --
+// S->reserved counts the footprint of every running problem plus the bytes
+// each idle worker context still holds (its grow-only buffers are kept
+// between problems so that equal-sized problems do not re-allocate).  A
+// problem runs on worker w either next to w's held buffers (held + footprint
+// is a bound on what w holds while it runs) or after w has released them; an
+// idle worker that holds memory while a queued problem does not fit releases
+// its buffers, so every problem within the budget is admitted eventually.
 void worker_loop(Server* S, int w) {
   hotrg_ctx* c = S->workers[w];
+  size_t& hold = S->hold[w];
   for (;;) {
     std::shared_ptr<Request> r;
+    bool release = false;
     {
       std::unique_lock<std::mutex> lk(S->mu);
       for (;;) {
         if (S->stop) return;
+        const size_t others = S->reserved - hold;
         // first queued request that fits; the oldest may be passed over at
         // most kMaxSkips times
         auto pick = S->queue.end();
         for (auto it = S->queue.begin(); it != S->queue.end(); ++it) {
-          if (S->reserved + (*it)->footprint <= S->budget) {
+          const size_t f = (*it)->footprint;
+          if (others + hold + f <= S->budget || others + f <= S->budget) {
             pick = it;
+            release = others + hold + f > S->budget;
             break;
           }
-          if (it == S->queue.begin()) {
-            if ((*it)->skips >= kMaxSkips) break;
-          }
+          if (it == S->queue.begin() && (*it)->skips >= kMaxSkips) break;
         }
         if (pick != S->queue.end()) {
           if (pick != S->queue.begin()) {
@@ -174,25 +186,58 @@ void worker_loop(Server* S, int w) {
           S->queue.erase(pick);
           break;
         }
+        if (!S->queue.empty() && hold > 0) {
+          release = true;  // what this idle worker holds may be what is missing
+          break;
+        }
         if (!S->queue.empty()) ++S->stalls;
         S->cv.wait(lk);
       }
-      r->state = Q_RUNNING;
-      S->reserved += r->footprint;
-      S->peak_reserved = std::max(S->peak_reserved, S->reserved);
-      ++S->admitted;
-      r->out->t_start = ctx_seconds(S->parent);
+      if (r) {
+        r->state = Q_RUNNING;
+        S->reserved += r->footprint;
+        S->peak_reserved = std::max(S->peak_reserved, S->reserved);
+        ++S->admitted;
+        r->out->t_start = ctx_seconds(S->parent);
+      }
     }
+    if (release) {
+      ctx_trim(c);
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->reserved -= hold;
+      hold = 0;
+      S->cv.notify_all();
+    }
+    if (!r) continue;
     hotrg_status st = run_problem(c, &r->params, &r->opts, r->out, &r->cancel);
+    r->out->prec_used = r->opts.prec;
     std::string err = st == HOTRG_OK ? "" : last_error_text();
-    if (ctx_budget(S->parent) > 0) ctx_trim(c);  // keep the held memory within the budget
+    const size_t held = hotrg_ctx_bytes_in_use(c);
+    const bool retry = st == HOTRG_ERR_NUMERIC && r->opts.prec != HOTRG_FP64 && !r->retried &&
+                       !r->cancel.load();
+    hotrg_opts o64 = r->opts;
+    o64.prec = HOTRG_FP64;
+    const size_t f64 = retry ? footprint_of(&r->params, &o64) : 0;
     {
       std::lock_guard<std::mutex> lk(S->mu);
+      S->reserved -= r->footprint + hold;
+      hold = held;
+      S->reserved += hold;
+      if (retry && f64 <= S->budget) {
+        // reduced-precision noise drove the run off: queue it once more in FP64
+        r->opts = o64;
+        r->footprint = f64;
+        r->retried = true;
+        r->state = Q_QUEUED;
+        r->skips = 0;
+        S->queue.push_front(r);
+        S->cv.notify_all();
+        continue;
+      }
       r->out->t_end = ctx_seconds(S->parent);
       r->status = st;
       r->err = err;
       r->state = Q_DONE;
-      S->reserved -= r->footprint;
     }
     S->cv.notify_all();
     S->done_cv.notify_all();
@@ -222,6 +267,7 @@ Server* server_of(hotrg_ctx* c, bool create) {
     delete S;
     return nullptr;
   }
+  S->hold.assign(S->workers.size(), 0);
   for (int i = 0; i < (int)S->workers.size(); ++i) S->threads.emplace_back(worker_loop, S, i);
   slot = S;
   return S;

@@ -18,7 +18,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__)
 sys.path.insert(0, ROOT)
 
 from oracle import hotrg, tensors, exact  # noqa: E402
-from tests.sensitivity import spectra_drift  # noqa: E402
+from tests.sensitivity import oracle_drift, spectra_drift  # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 BETA_C = math.log(1.0 + math.sqrt(2.0)) / 2.0
@@ -85,8 +85,9 @@ def xy_batch():
         res = hotrg.run(tensors.xy(beta, n_max), d_cut, 25, trunc="multiplet",
                         tau=1e-10, spec_len=d_cut + 1)
         rec = _record(res, d_cut + 1)
-        rec["spectra_drift"], _ = spectra_drift(tensors.xy(beta, n_max), d_cut, 25, d_cut + 1,
-                                                trunc="multiplet", base=res)
+        drift, lnz_drift, kept_pert, _ = oracle_drift(tensors.xy(beta, n_max), d_cut, 25,
+                                                      d_cut + 1, trunc="multiplet", base=res)
+        rec.update(spectra_drift=drift, lnz_drift=lnz_drift, kept_perturbed=kept_pert)
         rec.update(index=i, beta=beta, n_max=n_max, d_cut=d_cut, n_steps=25,
                    trunc="multiplet", tau=1e-10, seconds=time.time() - t)
         runs.append(rec)

@@ -114,16 +114,27 @@ def test_xy_batch_vs_stored_oracle(torch_cuda):
     with Context(0) as ctx:
         got, st = hotrg_run_batch(ctx, params, opts, with_steps=True)
     assert st == [0] * len(runs)
-    from tests.sensitivity import spectra_tolerances
+    from tests.sensitivity import lnz_tolerance, spectra_tolerances
 
     for r, g in zip(runs, got):
+        # XY spectra hold exact multiplets, and at some couplings a gap at
+        # the cut sits near the multiplet threshold: a one-rounding change of
+        # the environment then moves the oracle itself by far more than
+        # 1e-12, so both tolerances come from that measured drift
         rel = abs(g["lnz_per_site"] - r["lnz_per_site"]) / abs(r["lnz_per_site"])
-        assert rel <= 1e-12, (r["index"], rel)
+        say("xy", r["index"], "rel", rel, "drift", r["lnz_drift"])
+        assert rel <= lnz_tolerance(r["lnz_drift"]), (r["index"], rel)
         tol = spectra_tolerances(r["spectra_drift"])
+        stable = [a["kept"] == b for a, b in zip(r["steps"], r["kept_perturbed"])]
         for k, (gs, ws) in enumerate(zip(g["spectra"], r["spectra"])):
+            if not all(stable[:k]):
+                break  # an earlier cut is not fixed by the oracle either
             n = min(len(gs), len(ws))
             assert np.abs(np.asarray(gs[:n]) - np.asarray(ws[:n])).max() <= tol[k], (r["index"], k)
-        assert [s["kept"] for s in g["steps"]] == [s["kept"] for s in r["steps"]]
+        for k, (a, b) in enumerate(zip(g["steps"], r["steps"])):
+            if not all(stable[:k + 1]):
+                break
+            assert a["kept"] == b["kept"], (r["index"], k)
 
 
 def test_serving_stream_budget_cancel(torch_cuda):
@@ -187,3 +198,27 @@ def test_footprint_bounds_held_memory(torch_cuda):
         fp = hotrg_footprint(p, o)
         say("held", held, "footprint", fp)
         assert held <= fp
+
+
+def test_numeric_failure_reruns_in_fp64(torch_cuda):
+    # XY deep in the low-temperature phase: split-BF16 rounding breaks the
+    # charge structure and the flow runs off (a non-positive final trace);
+    # the serving loop re-runs such a request once in FP64.  Whichever way
+    # this request ends, its value must be the FP64 one or close to it.
+    from paper_2306_00358_amd import (HOTRG_BF16X3, HOTRG_FP64, Context, Ticket, hotrg_run,
+                                      make_opts, model_params)
+
+    p = model_params("xy", beta=1.1541, n_max=4)
+    o = make_opts(32, 36, prec="bf16x3", trunc="multiplet", degen_tol=1e-6)
+    o64 = make_opts(32, 36, prec="fp64", trunc="multiplet", degen_tol=1e-6)
+    with Context(0) as ctx:
+        ctx.set_workers(2)
+        got = Ticket(ctx, p, o).value()
+        want = hotrg_run(ctx, p, o64)["lnz_per_site"]
+    say("prec_used", got["prec_used"], got["lnz_per_site"], want)
+    assert math.isfinite(got["lnz_per_site"])
+    if got["prec_used"] == HOTRG_FP64:
+        assert got["lnz_per_site"] == want
+    else:
+        assert got["prec_used"] == HOTRG_BF16X3
+        assert abs(got["lnz_per_site"] - want) <= 1e-4 * abs(want)
