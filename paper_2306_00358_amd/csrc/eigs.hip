@@ -17,7 +17,9 @@
 // Check:      H = V (V M)^T, H = Z diag(theta) Z^T (rocSOLVER on p x p),
 //             Ritz vectors X = Z^T V, residuals |(Z^T Y)_i - theta_i X_i|.
 // Converged when the residuals of the `need` leading pairs are below
-// tol * theta_1; otherwise the sweeps continue from X.  All products are
+// tol * theta_1; otherwise the sweeps continue from X.  The first check
+// comes after q_first sweeps (the caller passes the count the previous
+// solve of the same kind needed, so most solves take one Rayleigh-Ritz).  All products are
 // FP64 MFMA GEMMs; the host reads p Ritz values and residuals per check.
 #include <hip/hip_runtime.h>
 #include <rocblas/rocblas.h>
@@ -44,77 +46,234 @@ __global__ void k_seed_block(double* V, long long count, unsigned long long seed
 }
 
 // G (p x p, row-major) -> RinvT = (R^-1)^T where G + s I = R^T R, s =
-// shift_rel * trace(G).  One workgroup of 1024 threads (32 x 32); G lives
-// in LDS (p <= 128).  Right-looking Cholesky: column j updates the trailing
-// upper triangle with the unscaled row j divided by its pivot, while row j
-// of R is written, scaled, into the strict lower triangle (as R^T) and the
-// pivots into rdiag -- one barrier per column.  Then Gauss-Jordan on the
-// upper triangle: X = R^-1 from X = I eliminating columns p-1 .. 0, again
-// one barrier per column (row k is scaled one column later, when nothing
-// reads it any more).  *fail is set if a pivot is not positive.
-__global__ __launch_bounds__(1024) void k_chol_inv(const double* __restrict__ G, int p,
-                                                   double shift_rel, double* __restrict__ RinvT,
-                                                   int* fail) {
-  extern __shared__ double A[];  // p * p, then rdiag (p), then 1024 scratch
-  double* rdiag = A + p * p;
-  double* red = rdiag + p;
+// shift_rel * trace(G).  One workgroup of 256 threads as a 16 x 16 grid;
+// thread (ty, tx) keeps the elements (ty + 16a, tx + 16b), a, b < 8, of the
+// working matrix in registers (p <= 128, p a multiple of 16; indices past p
+// are clamped, and those registers are never published or stored).
+//
+// Blocked right-looking Cholesky with blocks of 8 columns: the owners of the
+// block's 8 rows (final by then) publish them in LDS; thread c < p then
+// factors the 8 x 8 diagonal block itself (the same operations on the same
+// data in every such thread) and forms column c of the block rows of R by
+// forward substitution, straight into R in LDS; after a second barrier every
+// thread applies the rank-8 update to its elements.  The inverse X = R^-1 is
+// eliminated from X = I block by block from the bottom the same way: thread c
+// back-substitutes column c of the block's rows in place, and every row takes
+// the rank-8 update with column j0.. of R (zero below the diagonal, so rows
+// at and below the block are left alone; the block's rows then take their
+// final values).  Two barriers per block of 8 columns.
+//
+// R starts as zeros in LDS, so every load below is unconditional: rows and
+// columns that are already finished take updates nobody reads again, which
+// costs less than the waits a load under a branch would.  X^T leaves through
+// LDS for coalesced stores.  *fail is set if a pivot is not positive.
+constexpr int kCholThreads = 256;
+
+__global__ __launch_bounds__(kCholThreads) void k_chol_inv(const double* __restrict__ G, int p,
+                                                           double shift_rel,
+                                                           double* __restrict__ RinvT,
+                                                           int* fail) {
+  extern __shared__ double lds[];
+  double* R = lds;             // p * p: R (upper, zeros below), later X^T
+  double* P = R + p * p;       // 2 x 8 x 128 published rows
+  __shared__ int bad;
   const int t = threadIdx.x;
-  const int tx = t & 31, ty = t >> 5;
+  const int tx = t & 15, ty = t >> 4;
+  const int pm = p - 1;
+  for (int e = t; e < p * p; e += kCholThreads) R[e] = 0.0;
+  double A[8][8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const int i = min(ty + 16 * a, pm), k = min(tx + 16 * b, pm);
+      A[a][b] = G[min(i, k) * p + max(i, k)];  // upper part, mirrored
+    }
+  // trace: the diagonal owners publish, every thread sums in the same order
+  if (tx == ty) {
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+      if (ty + 16 * a < p) P[ty + 16 * a] = A[a][a];
+  }
+  if (t == 0) bad = 0;
+  __syncthreads();
   double tr = 0.0;
-  for (int i = ty; i < p; i += 32)
-    for (int j = tx; j < p; j += 32) {
-      const double v = i <= j ? G[i * p + j] : G[j * p + i];  // upper part, mirrored
-      A[i * p + j] = v;
-      if (i == j) tr += v;
-    }
-  red[t] = tr;
-  __syncthreads();
-  for (int o = 512; o > 0; o >>= 1) {
-    if (t < o) red[t] += red[t + o];
-    __syncthreads();
+  for (int i = 0; i < p; ++i) tr += P[i];
+  const double shift = shift_rel * tr;
+  if (tx == ty) {
+#pragma unroll
+    for (int a = 0; a < 8; ++a) A[a][a] += shift;
   }
-  const double shift = shift_rel * red[0];
-  if (t < p) A[t * p + t] += shift;
-  __syncthreads();
-  for (int j = 0; j < p; ++j) {
-    const double d = A[j * p + j];
-    if (!(d > 0.0)) {
+  __syncthreads();  // everyone has read the trace before P is reused
+
+  const int nblk = p >> 3;
+  for (int J = 0; J < nblk; ++J) {
+    const int j0 = 8 * J, aj = j0 >> 4, tj = j0 & 15;
+    double* Pb = P + (J & 1) * 1024;
+    if (ty >= tj && ty < tj + 8) {
+#pragma unroll
+      for (int a = 0; a < 8; ++a)
+        if (a == aj) {
+#pragma unroll
+          for (int b = 0; b < 8; ++b) Pb[(ty - tj) * 128 + tx + 16 * b] = A[a][b];
+        }
+    }
+    __syncthreads();
+    if (t < p && t >= j0) {
+      // the 8 x 8 diagonal block: L[r][c] (c >= r) becomes R[j0+r][j0+c]
+      double L[8][8], inv[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r)
+#pragma unroll
+        for (int c = r; c < 8; ++c) L[r][c] = Pb[r * 128 + j0 + c];
+      bool ok = true;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const double d = L[r][r];
+        ok = ok && d > 0.0;
+        const double rd = sqrt(d > 0.0 ? d : 1.0);
+        inv[r] = 1.0 / rd;
+        L[r][r] = rd;
+#pragma unroll
+        for (int c = r + 1; c < 8; ++c) L[r][c] *= inv[r];
+#pragma unroll
+        for (int r2 = r + 1; r2 < 8; ++r2)
+#pragma unroll
+          for (int c = r2; c < 8; ++c) L[r2][c] -= L[r][r2] * L[r][c];
+      }
+      if (!ok) bad = 1;
+      if (t >= j0 + 8) {
+        double v[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          double w = Pb[r * 128 + t];
+#pragma unroll
+          for (int m = 0; m < r; ++m) w -= L[m][r] * v[m];
+          v[r] = w * inv[r];
+          R[(j0 + r) * p + t] = v[r];
+        }
+      } else {
+        const int cc = t - j0;  // column inside the block
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          double v = 0.0;
+#pragma unroll
+          for (int c = r; c < 8; ++c) v = cc == c ? L[r][c] : v;
+          R[(j0 + r) * p + t] = v;
+        }
+      }
+    }
+    __syncthreads();
+    if (bad) {
       if (t == 0) *fail = 1;
-      return;  // uniform: every thread reads the same pivot
+      return;  // uniform: every thread read the same flag after the barrier
     }
-    const double rd = sqrt(d), inv_d = 1.0 / d, inv_rd = 1.0 / rd;
-    // R^T column j (lower triangle) and the pivot
-    if (ty == 0) {
-      for (int k = j + 1 + tx; k < p; k += 32) A[k * p + j] = A[j * p + k] * inv_rd;
-      if (tx == 0) rdiag[j] = rd;
+    // register rows / columns whose indices all lie before j0 + 8 are
+    // finished: skip them (a uniform test)
+    double Ri[8][8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      if (16 * a + 15 < j0 + 8) continue;
+      const int i = min(ty + 16 * a, pm);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) Ri[a][r] = R[(j0 + r) * p + i];
     }
-    // trailing update of the upper triangle, rows/cols j+1 .. p-1
-    for (int i = j + 1 + ty; i < p; i += 32) {
-      const double aji = A[j * p + i] * inv_d;
-      for (int k = i + tx; k < p; k += 32) A[i * p + k] -= aji * A[j * p + k];
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      if (16 * b + 15 < j0 + 8) continue;
+      const int k = min(tx + 16 * b, pm);
+      double Rk[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) Rk[r] = R[(j0 + r) * p + k];
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        if (16 * a + 15 < j0 + 8) continue;
+        double v = A[a][b];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) v -= Ri[a][r] * Rk[r];
+        A[a][b] = v;
+      }
+    }
+  }
+  // X = I in registers
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int b = 0; b < 8; ++b) A[a][b] = (ty + 16 * a == tx + 16 * b) ? 1.0 : 0.0;
+  __syncthreads();  // the last reads of P and R rows are done
+  for (int J = nblk - 1; J >= 0; --J) {
+    const int j0 = 8 * J, aj = j0 >> 4, tj = j0 & 15;
+    double* Pb = P + (J & 1) * 1024;
+    if (ty >= tj && ty < tj + 8) {
+#pragma unroll
+      for (int a = 0; a < 8; ++a)
+        if (a == aj) {
+#pragma unroll
+          for (int b = 0; b < 8; ++b) Pb[(ty - tj) * 128 + tx + 16 * b] = A[a][b];
+        }
     }
     __syncthreads();
-  }
-  // X = R^-1 in the upper triangle; R[i][k] = A[k*p + i] for i < k
-  for (int i = ty; i < p; i += 32)
-    for (int c = i + tx; c < p; c += 32) A[i * p + c] = i == c ? 1.0 : 0.0;
-  __syncthreads();
-  for (int k = p - 1; k >= 0; --k) {
-    const double inv_rkk = 1.0 / rdiag[k];
-    if (k + 1 < p && ty == 31)  // scale row k+1 (final since the last column)
-      for (int c = k + 1 + tx; c < p; c += 32) A[(k + 1) * p + c] /= rdiag[k + 1];
-    for (int i = ty; i < k; i += 32) {
-      const double f = A[k * p + i] * inv_rkk;  // R[i][k] / R[k][k]
-      for (int c = k + tx; c < p; c += 32) A[i * p + c] -= f * A[k * p + c];
+    if (t < p) {  // column t of the block rows, back substitution in place
+      double L[8][8], inv[8], x[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+#pragma unroll
+        for (int c = r; c < 8; ++c) L[r][c] = R[(j0 + r) * p + j0 + c];
+        inv[r] = 1.0 / L[r][r];
+        x[r] = Pb[r * 128 + t];
+      }
+#pragma unroll
+      for (int r = 7; r >= 0; --r) {
+        double v = x[r];
+#pragma unroll
+        for (int m = r + 1; m < 8; ++m) v -= L[r][m] * x[m];
+        x[r] = v * inv[r];
+        Pb[r * 128 + t] = x[r];
+      }
     }
     __syncthreads();
+    // X is upper triangular: the block's rows vanish before column j0, and
+    // rows from j0 + 8 on are final; skip those register groups (uniform)
+    double Xb[8][8];  // the block's final rows at the thread's own columns
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      if (16 * b + 15 < j0) continue;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) Xb[b][r] = Pb[r * 128 + tx + 16 * b];
+    }
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      if (16 * a >= j0 + 8) continue;
+      const int i = ty + 16 * a;
+      const int ic = min(i, pm);
+      double Rr[8];  // R[i][j0 + r]: zero for rows at or below the block
+#pragma unroll
+      for (int r = 0; r < 8; ++r) Rr[r] = R[ic * p + j0 + r];
+      const bool in_blk = i >= j0 && i < j0 + 8;
+      const int rb = i - j0;
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        if (16 * b + 15 < j0) continue;
+        double v = A[a][b];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) v -= Rr[r] * Xb[b][r];
+        double xr = Xb[b][0];
+#pragma unroll
+        for (int r = 1; r < 8; ++r) xr = rb == r ? Xb[b][r] : xr;
+        A[a][b] = in_blk ? xr : v;
+      }
+    }
   }
-  if (ty == 0)
-    for (int c = tx; c < p; c += 32) A[c] /= rdiag[0];
+  __syncthreads();  // all reads of R are done: reuse it for X^T
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const int i = ty + 16 * a, k = tx + 16 * b;
+      if (i < p && k < p) R[k * p + i] = A[a][b];
+    }
   __syncthreads();
-  // RinvT[i][k] = X[k][i] (lower triangular)
-  for (int i = ty; i < p; i += 32)
-    for (int k = tx; k < p; k += 32) RinvT[i * p + k] = k <= i ? A[k * p + i] : 0.0;
+  for (int e = t; e < p * p; e += kCholThreads) RinvT[e] = R[e];
 }
 
 __global__ void k_symmetrize_small(double* H, int p) {
@@ -174,41 +333,51 @@ static inline int splitk_chunk(int K) {
   return c < 16 ? 16 : c;
 }
 
+// K chunk of the block products V M (p x n times n x n): four partial
+// products, so that p = 128 rows still give 4 x 2 x (n / 64) workgroups
+static inline int vm_chunk(int n) { return ((n + 3) / 4 + 15) / 16 * 16; }
+
+static inline size_t partial_doubles(int n, int p) {
+  const size_t pn = (size_t)p * n, pp = (size_t)p * p;
+  const size_t gram = (size_t)((n + splitk_chunk(n) - 1) / splitk_chunk(n)) * pp;
+  const size_t vm = (size_t)((n + vm_chunk(n) - 1) / vm_chunk(n)) * pn;
+  return gram > vm ? gram : vm;
+}
+
 size_t topk_workspace_doubles(int n, int p) {
   const size_t pn = (size_t)p * n, pp = (size_t)p * p;
-  const int parts = (n + splitk_chunk(n) - 1) / splitk_chunk(n);
-  return 4 * pn + (size_t)parts * pp + 4 * pp + 4 * (size_t)p + 16;
+  return 4 * pn + partial_doubles(n, p) + 4 * pp + 4 * (size_t)p + 16;
 }
 
 // Returns true and leaves theta (ascending, p values) in W and the Ritz
 // vectors (rows, same order) in Xout (p x n) on convergence.
 bool topk_eigs(rocblas_handle blas, const double* M, int n, int p, int need, double tol,
-               double* ws, double* W, double* Xout, int* dinfo, int* iters, double* resid,
-               hipStream_t s) {
+               int q_first, double* ws, double* W, double* Xout, int* dinfo, int* iters,
+               double* resid, hipStream_t s) {
   const size_t pn = (size_t)p * n, pp = (size_t)p * p;
   const int kc = splitk_chunk(n);
-  const int parts = (n + kc - 1) / kc;
+  const int kv = vm_chunk(n);
   double* V = ws;
   double* Y = V + pn;
   double* T2 = Y + pn;
   double* Yx = T2 + pn;
   double* part = Yx + pn;
-  double* G = part + (size_t)parts * pp;
+  double* G = part + partial_doubles(n, p);
   double* Rt = G + pp;
   double* H = Rt + pp;
   double* E = H + pp;          // p (tridiagonal work for dsyevd)
   double* res = E + pp;        // p
   int* fail = (int*)(res + p); // 1 int
-  const size_t lds = ((size_t)p * p + p + 1024) * sizeof(double);
+  const size_t lds = ((size_t)p * p + 2048) * sizeof(double);
   const double u = std::ldexp(1.0, -53);
   const double shift_rel = 11.0 * ((double)n * p + (double)p * (p + 1)) * u;
 
   static bool lds_set = [] {
     return hipFuncSetAttribute((const void*)k_chol_inv, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)(((size_t)128 * 128 + 128 + 1024) * sizeof(double))) ==
+                               (int)(((size_t)128 * 128 + 2048) * sizeof(double))) ==
            hipSuccess;
   }();
-  if (!lds_set || p > 128) return false;
+  if (!lds_set || p > 128 || p % 16 != 0) return false;
   (void)hipMemsetAsync(fail, 0, sizeof(int), s);
   hipLaunchKernelGGL(k_seed_block, dim3(256), dim3(256), 0, s, V, (long long)pn, 12345ULL);
 
@@ -217,7 +386,7 @@ bool topk_eigs(rocblas_handle blas, const double* M, int n, int p, int need, dou
     const double* src = Yin;
     for (int pass = 0; pass < 3; ++pass) {
       gemm_f64_splitk(src, n, src, n, B_KCONTIG, G, p, p, p, n, kc, part, s);
-      hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(1024), lds, s, G, p,
+      hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(kCholThreads), lds, s, G, p,
                          pass == 0 ? shift_rel : 0.0, Rt, fail);
       double* dst = (pass == 2) ? Vout : (src == T2 ? Y : T2);
       if (dst == src) dst = (src == Y) ? T2 : Y;
@@ -226,18 +395,23 @@ bool topk_eigs(rocblas_handle blas, const double* M, int n, int p, int need, dou
     }
   };
 
-  int it = 0, q = 3;
+  // Y = V M
+  auto vm = [&](const double* Vin, double* Yout) {
+    gemm_f64_splitk(Vin, n, M, n, B_NCONTIG, Yout, n, p, n, n, kv, part, s);
+  };
+
+  int it = 0, q = q_first > 0 ? q_first : 3;
   const int max_it = 80;
   double prev = 1e300;
   std::vector<double> th(p), rs(p);
   while (true) {
     for (int r = 0; r < q; ++r) {
-      gemm_f64(V, n, M, n, B_NCONTIG, Y, out_rowmajor(n), p, n, n, nullptr, s);
+      vm(V, Y);
       orth(Y, V);
       ++it;
     }
     // Rayleigh-Ritz
-    gemm_f64(V, n, M, n, B_NCONTIG, Y, out_rowmajor(n), p, n, n, nullptr, s);
+    vm(V, Y);
     gemm_f64_splitk(V, n, Y, n, B_KCONTIG, H, p, p, p, n, kc, part, s);
     hipLaunchKernelGGL(k_symmetrize_small, dim3(16), dim3(256), 0, s, H, p);
     if (rocsolver_dsyevd(blas, rocblas_evect_original, rocblas_fill_lower, p, H, p, W, E, dinfo) !=

@@ -102,6 +102,8 @@ struct hotrg_state {
   Buf recs;            // device: 5 doubles per step
   Buf spec;            // device spectra, spec_cap doubles per step
   int rec_cap = 0, spec_len = 0;
+  // sweeps the last iterative eigensolve of each step parity needed, and its n
+  int eig_sweeps[2] = {0, 0}, eig_n[2] = {0, 0};
 };
 
 namespace {
@@ -502,9 +504,15 @@ void do_step(hotrg_ctx* c, hotrg_state* st, const hotrg_opts* o) {
     ensure(c, c->Xr, (size_t)p * n * 8);
     int iters = 0;
     double resid = 0.0;
-    sub = topk_eigs(c->blas, (const double*)c->M.p, n, p, need, 5e-14, (double*)c->EW.p,
-                    (double*)c->W.p, (double*)c->Xr.p, (int*)((char*)c->scal.p + 48), &iters,
-                    &resid, c->stream);
+    // steps of equal parity see environments of the same kind: start with
+    // one sweep more than the last such solve needed
+    const int par = st->k & 1;
+    const int q_first = st->eig_n[par] == n ? st->eig_sweeps[par] + 1 : 3;
+    sub = topk_eigs(c->blas, (const double*)c->M.p, n, p, need, 5e-14, q_first,
+                    (double*)c->EW.p, (double*)c->W.p, (double*)c->Xr.p,
+                    (int*)((char*)c->scal.p + 48), &iters, &resid, c->stream);
+    st->eig_n[par] = sub ? n : 0;
+    st->eig_sweeps[par] = iters;
     c->last_eig_iters = sub ? iters : 0;
     c->last_eig_resid = resid;
     if (sub) {

@@ -13,8 +13,8 @@
 // Output: FP32, split BF16 (for a following BF16X3 contraction) or FP64
 // (for the FP64 eigensolver).
 //
-// Tiling: 8 waves, 256 x 128 block tile, each wave 64 x 64 as 4 x 4 MFMA
-// tiles; K slabs of 32 elements streamed into LDS with
+// Tiling: 8 waves, 256 x 256 block tile, each wave 128 x 64 as 8 x 4 MFMA
+// tiles (256 x 128 and 64 x 64 per wave when N < 256); K slabs of 32 elements streamed into LDS with
 // global_load_lds_dwordx4 (16 bytes per lane), two LDS stages.  An LDS row
 // is 128 bytes = 8 chunks of 16 bytes: for RP_F32 the 32 floats of the slab,
 // for RP_BF16X3 four hi chunks then four lo chunks (8 bf16 each).  Chunk c
@@ -27,6 +27,8 @@
 // the 32 k of a slab are split by lane group: group g owns k in [8g, 8g+8),
 // one k per MFMA; for BF16 group g owns the same 8 k in one MFMA.
 #include <hip/hip_runtime.h>
+
+#include <cstdlib>
 
 #include "internal.h"
 
@@ -79,7 +81,9 @@ __device__ __forceinline__ void rp_load(const void* __restrict__ hi, const void*
   }
 }
 
-template <int MODE, int OUT, int TAG>
+// Block tile 256 x BN with 8 waves; each wave owns 16 TM rows x 64 columns
+// (TM MFMA tiles of 16 rows): TM = 4 for BN = 128, TM = 8 for BN = 256.
+template <int MODE, int OUT, int TAG, int TM, int BN>
 __global__ __launch_bounds__(512) void k_gemm_rp(const void* __restrict__ Ahi,
                                                  const void* __restrict__ Alo, long long lda,
                                                  const void* __restrict__ Bhi,
@@ -87,19 +91,21 @@ __global__ __launch_bounds__(512) void k_gemm_rp(const void* __restrict__ Ahi,
                                                  void* __restrict__ C, void* __restrict__ Clo,
                                                  OutMap om, int M, int N, int K,
                                                  unsigned long long* maxbits) {
-  constexpr int BM = 256, BN = 128, A_BYTES = BM * 128, B_BYTES = BN * 128;
+  constexpr int BM = 256, A_BYTES = BM * 128, B_BYTES = BN * 128;
   constexpr int STAGE = A_BYTES + B_BYTES;
+  constexpr int WN = BN / 64;               // waves along N
+  static_assert((BM / (16 * TM)) * WN == 8, "8 waves per block");
   constexpr int LOADS = BM / 64 + BN / 64;  // per wave per slab
-  __shared__ __attribute__((aligned(16))) char smem[2 * STAGE];
+  extern __shared__ __attribute__((aligned(16))) char smem[];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / WN, wn = wave % WN;
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
   const int li = lane & 15, lg = lane >> 4;
 
-  f4 acc[4][4];
+  f4 acc[TM][4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < TM; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
@@ -126,10 +132,10 @@ __global__ __launch_bounds__(512) void k_gemm_rp(const void* __restrict__ Ahi,
     asm volatile("" ::: "memory");
     const char* as = smem + cur * STAGE;
     const char* bs = as + A_BYTES;
-    f4 a0[4], a1[4], b0[4], b1[4];
+    f4 a0[TM], a1[TM], b0[4], b1[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int r = wm * 64 + i * 16 + li;
+    for (int i = 0; i < TM; ++i) {
+      const int r = wm * 16 * TM + i * 16 + li;
       a0[i] = *(const f4*)(as + r * 128 + ((c0 ^ rp_swz(r)) << 4));
       a1[i] = *(const f4*)(as + r * 128 + ((c1 ^ rp_swz(r)) << 4));
     }
@@ -143,7 +149,7 @@ __global__ __launch_bounds__(512) void k_gemm_rp(const void* __restrict__ Ahi,
 #pragma unroll
       for (int t = 0; t < 8; ++t)
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < TM; ++i)
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
             const float av = t < 4 ? a0[i][t] : a1[i][t - 4];
@@ -152,7 +158,7 @@ __global__ __launch_bounds__(512) void k_gemm_rp(const void* __restrict__ Ahi,
           }
     } else {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
+      for (int i = 0; i < TM; ++i) {
         const bf8 ah = __builtin_bit_cast(bf8, a0[i]);
         const bf8 al = __builtin_bit_cast(bf8, a1[i]);
 #pragma unroll
@@ -180,10 +186,10 @@ __global__ __launch_bounds__(512) void k_gemm_rp(const void* __restrict__ Ahi,
     coff[j] = cok[j] ? rmap_col(om, n) : 0;
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < TM; ++i) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int m = m0 + wm * 64 + i * 16 + 4 * lg + v;
+      const int m = m0 + wm * 16 * TM + i * 16 + 4 * lg + v;
       if (m >= M) continue;
       const long long roff = rmap_row(om, m);
 #pragma unroll
@@ -211,20 +217,46 @@ __global__ __launch_bounds__(512) void k_gemm_rp(const void* __restrict__ Ahi,
   }
 }
 
+// block width: 256 columns (wave tile 128 x 64) when N allows, else 128
+static int rp_block_n(int N) {
+  static const int forced = [] {
+    const char* e = getenv("HOTRG_RP_BN");
+    return e ? atoi(e) : 0;
+  }();
+  if (forced == 128 || forced == 256) return forced;
+  return N >= 256 ? 256 : 128;
+}
+
+template <int MODE, int OUT, int TM, int BN>
+static void launch_rp_shape(int tag, const RpOperand& A, long long lda, const RpOperand& B,
+                            long long ldb, void* C, void* Clo, const OutMap& om, int M, int N,
+                            int K, unsigned long long* maxbits, hipStream_t s) {
+  constexpr int LDS = 2 * (256 + BN) * 128;
+  dim3 grid((N + BN - 1) / BN, (M + 255) / 256);
+  auto go = [&](auto kern) {
+    static const bool ok = hipFuncSetAttribute((const void*)kern,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               LDS) == hipSuccess;
+    (void)ok;
+    hipLaunchKernelGGL(kern, grid, dim3(512), LDS, s, A.hi, A.lo, lda, B.hi, B.lo, ldb, C, Clo,
+                       om, M, N, K, maxbits);
+  };
+  if (tag == GEMM_TAG_C2)
+    go(k_gemm_rp<MODE, OUT, GEMM_TAG_C2, TM, BN>);
+  else if (tag == GEMM_TAG_ENV)
+    go(k_gemm_rp<MODE, OUT, GEMM_TAG_ENV, TM, BN>);
+  else
+    go(k_gemm_rp<MODE, OUT, GEMM_TAG_OTHER, TM, BN>);
+}
+
 template <int MODE, int OUT>
 static void launch_rp_tag(int tag, const RpOperand& A, long long lda, const RpOperand& B,
                           long long ldb, void* C, void* Clo, const OutMap& om, int M, int N,
                           int K, unsigned long long* maxbits, hipStream_t s) {
-  dim3 grid((N + 127) / 128, (M + 255) / 256);
-  if (tag == GEMM_TAG_C2)
-    hipLaunchKernelGGL((k_gemm_rp<MODE, OUT, GEMM_TAG_C2>), grid, dim3(512), 0, s, A.hi, A.lo, lda,
-                       B.hi, B.lo, ldb, C, Clo, om, M, N, K, maxbits);
-  else if (tag == GEMM_TAG_ENV)
-    hipLaunchKernelGGL((k_gemm_rp<MODE, OUT, GEMM_TAG_ENV>), grid, dim3(512), 0, s, A.hi, A.lo,
-                       lda, B.hi, B.lo, ldb, C, Clo, om, M, N, K, maxbits);
+  if (rp_block_n(N) == 256)
+    launch_rp_shape<MODE, OUT, 8, 256>(tag, A, lda, B, ldb, C, Clo, om, M, N, K, maxbits, s);
   else
-    hipLaunchKernelGGL((k_gemm_rp<MODE, OUT, GEMM_TAG_OTHER>), grid, dim3(512), 0, s, A.hi, A.lo,
-                       lda, B.hi, B.lo, ldb, C, Clo, om, M, N, K, maxbits);
+    launch_rp_shape<MODE, OUT, 4, 128>(tag, A, lda, B, ldb, C, Clo, om, M, N, K, maxbits, s);
 }
 
 bool gemm_rp(int mode, const RpOperand& A, long long lda, const RpOperand& B, long long ldb,
