@@ -36,6 +36,20 @@ def ising(beta, J=1.0):
     return T
 
 
+def _charge_tensor(w):
+    """T[a,b,c,d] = w[a] w[b] w[c] w[d] where the charges obey
+    n_a + n_b = n_c + n_d (index = charge + n_max), zero elsewhere."""
+    D = len(w)
+    T = np.zeros((D, D, D, D), dtype=np.float64)
+    for a in range(D):
+        for b in range(D):
+            for c in range(D):
+                d = a + b - c  # n_d = n_a + n_b - n_c, as an index shift
+                if 0 <= d < D:
+                    T[a, b, c, d] = w[a] * w[b] * w[c] * w[d]
+    return T
+
+
 def xy(beta, n_max):
     """Classical XY tensor from the character expansion (Sec. 3.1 with
     Delta = 1, h = 0; the paper notes its index range is infinite and must be
@@ -49,17 +63,37 @@ def xy(beta, n_max):
     """
     if n_max < 0:
         raise ValueError("n_max must be >= 0")
-    D = 2 * n_max + 1
     n = np.arange(-n_max, n_max + 1)
-    w = np.sqrt(iv(n, beta))
-    T = np.zeros((D, D, D, D), dtype=np.float64)
-    for a in range(D):
-        for b in range(D):
-            for c in range(D):
-                d = a + b - c  # n_d = n_a + n_b - n_c, as an index shift
-                if 0 <= d < D:
-                    T[a, b, c, d] = w[a] * w[b] * w[c] * w[d]
-    return T
+    return _charge_tensor(np.sqrt(iv(n, beta)))
+
+
+def gxy_weights(beta, delta, n_max):
+    """Character coefficients c_n, |n| <= n_max, of the generalized XY bond
+    weight exp(beta*delta*cos(phi) + beta*(1-delta)*cos(2 phi)) (Sec. 3.1,
+    Eq. (gXY_ham) with h = 0).
+
+    exp(x cos phi) = sum_k I_k(x) e^{i k phi} and
+    exp(y cos 2phi) = sum_m I_m(y) e^{2 i m phi}; the coefficient of e^{i n phi}
+    in their product is c_n = sum_m I_{n-2m}(x) I_m(y), x = beta*delta,
+    y = beta*(1-delta).  The terms fall off like (x/2)^|k| / |k|! times
+    (y/2)^|m| / |m|!, so |m| <= n_max + 40 is exact in FP64 for beta of
+    order one.
+    """
+    if n_max < 0:
+        raise ValueError("n_max must be >= 0")
+    if not 0.0 <= delta <= 1.0 or beta < 0:
+        raise ValueError("need 0 <= delta <= 1 and beta >= 0")
+    x, y = beta * delta, beta * (1.0 - delta)
+    m = np.arange(-(n_max + 40), n_max + 41)
+    c = np.array([np.sum(iv(n - 2 * m, x) * iv(m, y)) for n in range(-n_max, n_max + 1)])
+    return c
+
+
+def gxy(beta, delta, n_max):
+    """Generalized XY tensor (Sec. 3.1): the XY construction with the bond
+    weights I_n(beta) replaced by the coefficients c_n of ``gxy_weights``
+    (delta = 1 is the XY model, delta = 0 the pure nematic coupling)."""
+    return _charge_tensor(np.sqrt(gxy_weights(beta, delta, n_max)))
 
 
 def potts(beta, q):

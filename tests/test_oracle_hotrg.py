@@ -296,3 +296,31 @@ def test_coarse_tensor_slice_matches_full():
     full = hotrg.coarse_tensor(T, U)
     for i, k in [(0, 0), (2, 4), (4, 1)]:
         assert np.abs(hotrg.coarse_tensor_slice(T, U, i, k) - full[i, :, k, :]).max() <= 1e-12
+
+
+def test_gxy_nematic_limit_is_xy():
+    # Delta = 0: the weight depends on 2(theta_i - theta_j) only, so theta -> 2 theta maps
+    # the model onto XY at the same beta; in the tensor network the odd charges carry
+    # zero weight and the even ones are the XY tensor (n_max = 2m against m)
+    a = hotrg.run(tensors.gxy(1.0, 0.0, 4), 10, 8, trunc="multiplet", tau=1e-10)
+    b = hotrg.run(tensors.xy(1.0, 2), 10, 8, trunc="multiplet", tau=1e-10)
+    assert a.lnz_per_site == pytest.approx(b.lnz_per_site, rel=1e-12)
+
+
+def test_gxy_untruncated_one_step_equals_charge_sum_and_quadrature():
+    # 1x2 torus (one vertical step, untruncated).  Charge conservation at a
+    # site forces the two vertical bonds to carry the same charge, so
+    # Z = (sum_n c_n)^2 * sum_n c_n^2 over the kept charges; with many charges
+    # the same sum is the angle integral of the four bond weights.  The
+    # nematic coefficients fall off only like (beta(1-delta)/2)^(n/2) / (n/2)!,
+    # so the quadrature comparison uses n_max = 40 on the weights alone.
+    beta, delta = 0.9, 0.5
+    c = tensors.gxy_weights(beta, delta, 3)
+    r = hotrg.run(tensors.gxy(beta, delta, 3), UNTRUNCATED, 1)
+    assert r.lnz_per_site == pytest.approx(np.log(c.sum() ** 2 * (c * c).sum()) / 2, rel=1e-13)
+    c = tensors.gxy_weights(beta, delta, 40)
+    N = 96
+    th = 2 * np.pi * np.arange(N) / N
+    w = np.exp(beta * delta * np.cos(th) + beta * (1 - delta) * np.cos(2 * th))
+    Z = np.mean(w * w) * np.exp(2 * beta)  # two vertical bonds, two self-bonds at angle 0
+    assert c.sum() ** 2 * (c * c).sum() == pytest.approx(Z, rel=1e-13)

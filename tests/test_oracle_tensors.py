@@ -65,3 +65,30 @@ def test_potts_one_site_torus(q):
     T = tensors.potts(beta, q)
     # sum_sigma W[sigma, sigma]^2 = q e^(2 beta)
     assert np.einsum("ijij->", T) == pytest.approx(q * math.exp(2 * beta), rel=1e-13)
+
+
+@pytest.mark.parametrize("beta", [0.4, 1.1])
+def test_gxy_at_delta_one_is_xy(beta):
+    # Delta = 1 removes the nematic term: I_m(0) = delta_{m,0} leaves c_n = I_n
+    assert np.array_equal(tensors.gxy(beta, 1.0, 4), tensors.xy(beta, 4))
+
+
+@pytest.mark.parametrize("beta,delta", [(0.5, 0.2), (0.9, 0.5), (1.3, 0.8), (1.0, 0.0)])
+def test_gxy_weights_are_fourier_coefficients(beta, delta):
+    # c_n = (1/2pi) int exp(beta delta cos phi + beta (1-delta) cos 2phi) cos(n phi) dphi,
+    # by the trapezoid rule on the periodic integrand (exact to rounding at 512 points)
+    N = 512
+    phi = 2 * np.pi * np.arange(N) / N
+    f = np.exp(beta * delta * np.cos(phi) + beta * (1 - delta) * np.cos(2 * phi))
+    c = tensors.gxy_weights(beta, delta, 6)
+    for n in range(-6, 7):
+        want = np.mean(f * np.cos(n * phi))
+        assert c[n + 6] == pytest.approx(want, rel=1e-12, abs=1e-14 * c[6])
+
+
+def test_gxy_at_delta_zero_has_only_even_charges():
+    # Delta = 0: c_n = I_{n/2}(beta) for even n, 0 for odd n
+    c = tensors.gxy_weights(0.8, 0.0, 6)
+    for n in range(-6, 7):
+        want = iv(n // 2, 0.8) if n % 2 == 0 else 0.0
+        assert c[n + 6] == pytest.approx(want, rel=1e-15, abs=0.0)
