@@ -294,14 +294,14 @@ def cpu_baseline(d_cut):
     T = T / np.abs(T).max()
     k = 0
     while not (T.shape[0] == d_cut and T.shape[1] == d_cut):
-        Tt, _, _, _ = hotrg.directional_step(T, d_cut)
+        Tt = hotrg.directional_step(T, d_cut)[0]
         T = hotrg.rotate(Tt)
         T = T / np.abs(T).max()
         k += 1
         if k > 12:
             raise RuntimeError("steady state not reached")
     t0 = time.perf_counter()
-    Tt, _, _, _ = hotrg.directional_step(T, d_cut)
+    Tt = hotrg.directional_step(T, d_cut)[0]
     T = hotrg.rotate(Tt)
     T = T / np.abs(T).max()
     dt = time.perf_counter() - t0

@@ -8,6 +8,10 @@ Test infrastructure only (see ``oracle/__init__.py``).
                           form (textbook), independent of the 4F3 form.
 * ``onsager_tc``       -- the closed value at the critical point,
                           ln(2)/2 + 2G/pi with Catalan's constant G.
+* ``onsager_energy``   -- the internal energy per site in closed form
+                          (complete elliptic integral of the first kind).
+* ``onsager_specific_heat`` -- beta^2 d^2(-beta f)/d beta^2 of the 4F3 form,
+                          differentiated by mpmath at 40 digits.
 * ``ising_torus``      -- brute-force ln Z / N of the Ising model on an
                           Lx-by-Ly torus by a row transfer matrix.
 * ``xy_torus``         -- ln Z / N of the XY model on a tiny torus, the site
@@ -51,6 +55,35 @@ def onsager_integral(beta):
     val, _ = quad(f, 0.0, math.pi, epsabs=1e-15, epsrel=1e-15, limit=400,
                   points=[math.pi / 2])
     return math.log(2.0 * math.cosh(2 * beta)) + val / (2.0 * math.pi)
+
+
+def onsager_energy(beta):
+    """Internal energy per site u = -d(ln Z/N)/d beta of the 2D Ising model:
+    u = -coth(2beta) [1 + (2/pi)(2 tanh^2(2beta) - 1) K(k)],
+    k = 2 sinh(2beta) / cosh^2(2beta), K the complete elliptic integral of
+    the first kind of modulus k (Onsager 1944, as in standard texts).
+    u -> 0 as beta -> 0 and u -> -2 as beta -> infinity."""
+    from scipy.special import ellipk
+
+    t = math.tanh(2 * beta)
+    k = 2.0 * math.sinh(2 * beta) / math.cosh(2 * beta) ** 2
+    return -(1.0 / t) * (1.0 + (2.0 / math.pi) * (2.0 * t * t - 1.0) * float(ellipk(k * k)))
+
+
+def onsager_specific_heat(beta, dps=40):
+    """Specific heat per site c = beta^2 d^2(ln Z/N)/d beta^2 from the 4F3
+    form of ``onsager_hyper``, differentiated by mpmath at ``dps`` digits
+    (away from T_c, where c diverges logarithmically)."""
+    import mpmath as mp
+
+    with mp.workdps(dps):
+        def f(b):
+            kap = mp.sinh(2 * b) / (2 * mp.cosh(2 * b) ** 2)
+            F = mp.hyper([1, 1, mp.mpf(3) / 2, mp.mpf(3) / 2], [2, 2, 2], 16 * kap**2)
+            return mp.log(2 * mp.cosh(2 * b)) - kap**2 * F
+
+        b = mp.mpf(beta)
+        return float(b * b * mp.diff(f, b, 2))
 
 
 def onsager_tc():

@@ -50,6 +50,7 @@ class StepInfo:
     cut_gap: float    # (s_{D'} - s_{D'+1}) / s_1, or -1 when nothing is cut
     lnz_torus: float  # ln Z / N of the 2**k-site torus built so far
     kept: int         # columns of U that are not zero padding
+    side: int = 0     # environment the projector came from: 0 left, 1 right
 
 
 @dataclass
@@ -121,15 +122,48 @@ def coarse_tensor_slice(T, U3, i, k):
     return np.tensordot(L, R, axes=([0, 2, 3], [0, 3, 1]))     # (j, l)
 
 
-def directional_step(T, d_cut, trunc="plain", tau=1e-10):
+SIDE_MARGIN = 1e-12  # the two-sided choice takes the right side only when it is this much better
+
+
+def mirror(T):
+    """The tensor reflected left-right: legs (l, u, r, d) -> (r, u, l, d).
+    The environment of the mirrored tensor is the environment of the
+    original pair's two right legs, (second.right, first.right)."""
+    return np.ascontiguousarray(T.transpose(2, 1, 0, 3))
+
+
+def truncation_error(s, kept):
+    """1 - (sum of the kept singular values) / (sum of all of them)."""
+    return float(1.0 - s[:kept].sum() / s.sum())
+
+
+def directional_step(T, d_cut, trunc="plain", tau=1e-10, isometry="one"):
     """One directional coarse-graining: environment, projector, coarse
     tensor.  Returns (T~ with legs (l, u, r, d) of the merged pair,
-    singular values, D', kept)."""
+    singular values, D', kept, side).
+
+    ``isometry="one"`` is the paper's choice (Sec. 2): the projector comes
+    from the environment of the left pair of legs and truncates both pairs.
+    ``isometry="two"`` is the original HOTRG choice: the projectors of the
+    left and of the right environment are both formed and the one with the
+    smaller truncation error (epsilon_1 vs epsilon_2) is used for both
+    pairs.  The right one is taken only when its error is smaller by more
+    than SIDE_MARGIN: for tensors symmetric under reflection (Ising, Potts;
+    XY up to charge conjugation) the two errors agree up to rounding, and
+    the rule then keeps the left projector, as the one-sided method does.
+    """
     dx = T.shape[0]
     M = environment(T)
     U, s, d_new, kept = projector(M, d_cut, trunc, tau)
+    side = 0
+    if isometry == "two":
+        Ur, sr, _, kr = projector(environment(mirror(T)), d_cut, trunc, tau)
+        if truncation_error(sr, kr) < truncation_error(s, kept) - SIDE_MARGIN:
+            U, s, kept, side = Ur, sr, kr, 1
+    elif isometry != "one":
+        raise ValueError("isometry must be 'one' or 'two'")
     T_new = coarse_tensor(T, U.reshape(dx, dx, d_new))
-    return T_new, s, d_new, kept
+    return T_new, s, d_new, kept, side
 
 
 def rotate(T):
@@ -145,7 +179,7 @@ def torus_trace(T):
     return float(np.einsum("ijij->", T))
 
 
-def run(T0, d_cut, n_steps, trunc="plain", tau=1e-10, spec_len=None):
+def run(T0, d_cut, n_steps, trunc="plain", tau=1e-10, spec_len=None, isometry="one"):
     """Full HOTRG: K = n_steps directional steps from the initial tensor T0,
     then the periodic trace.  Returns ``Result`` with ln Z per site."""
     if d_cut < 1 or n_steps < 0:
@@ -159,7 +193,7 @@ def run(T0, d_cut, n_steps, trunc="plain", tau=1e-10, spec_len=None):
     res = Result(lnz_per_site=np.nan)
     for k in range(1, n_steps + 1):
         dx, dy = T.shape[0], T.shape[1]
-        Tt, s, d_new, kept = directional_step(T, d_cut, trunc, tau)
+        Tt, s, d_new, kept, side = directional_step(T, d_cut, trunc, tau, isometry)
         T = rotate(Tt)
         nk = np.abs(T).max()
         T = T / nk
@@ -167,9 +201,9 @@ def run(T0, d_cut, n_steps, trunc="plain", tau=1e-10, spec_len=None):
         tr = torus_trace(T)
         lnz_t = acc + 2.0 ** (-k) * np.log(tr) if tr > 0 else np.nan
         gap = (s[d_new - 1] - s[d_new]) / s[0] if d_new < s.size else -1.0
-        err = 1.0 - s[:kept].sum() / s.sum()
-        res.steps.append(StepInfo(dx, dy, d_new, float(np.log(nk)), float(err),
-                                  float(gap), float(lnz_t), kept))
+        err = truncation_error(s, kept)
+        res.steps.append(StepInfo(dx, dy, d_new, float(np.log(nk)), err,
+                                  float(gap), float(lnz_t), kept, side))
         L = s.size if spec_len is None else min(spec_len, s.size)
         res.spectra.append(s[:L] / s[0])
     tr = torus_trace(T)

@@ -67,3 +67,27 @@ def test_xy_torus_closed_forms(beta):
     assert exact.xy_torus(beta, 1, 1) == pytest.approx(2 * beta, rel=1e-14)
     want = (2 * beta + math.log(iv(0, 2 * beta))) / 2
     assert exact.xy_torus(beta, 1, 2) == pytest.approx(want, rel=1e-14)
+
+
+@pytest.mark.parametrize("beta", [0.2, 1.0 / 1.5, 0.3, 1.0 / 3.5])
+def test_onsager_energy_is_derivative_of_free_energy(beta):
+    # closed form (elliptic K) against mpmath's derivative of the 4F3 form
+    import mpmath as mp
+
+    with mp.workdps(40):
+        def f(b):
+            kap = mp.sinh(2 * b) / (2 * mp.cosh(2 * b) ** 2)
+            F = mp.hyper([1, 1, mp.mpf(3) / 2, mp.mpf(3) / 2], [2, 2, 2], 16 * kap**2)
+            return mp.log(2 * mp.cosh(2 * b)) - kap**2 * F
+
+        want = float(-mp.diff(f, mp.mpf(beta)))
+    assert exact.onsager_energy(beta) == pytest.approx(want, rel=1e-13)
+
+
+def test_onsager_energy_and_specific_heat_limits():
+    # high temperature: ln Z/N = ln 2 + 2 ln cosh(beta) + O(beta^4 tanh^4) -> u ~ -2 tanh(beta)
+    b = 1e-3
+    assert exact.onsager_energy(b) == pytest.approx(-2 * math.tanh(b), rel=1e-5)
+    assert exact.onsager_specific_heat(b) == pytest.approx(2 * b * b, rel=1e-4)
+    # ground state: u -> -2 J per site
+    assert exact.onsager_energy(5.0) == pytest.approx(-2.0, abs=1e-12)
