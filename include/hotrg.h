@@ -48,7 +48,11 @@ typedef enum {
   HOTRG_ISING = 0, /* Ising, bond dimension 2 (Sec. 3.2) */
   HOTRG_XY = 1,    /* classical XY, character expansion, |n| <= n_max (Sec. 3.1, Delta = 1) */
   HOTRG_POTTS = 2, /* q-state Potts, Cholesky split of the bond weight (Sec. 3.3) */
-  HOTRG_RAW = 3    /* caller-supplied initial tensor */
+  HOTRG_RAW = 3,   /* caller-supplied initial tensor */
+  HOTRG_GXY = 4    /* generalized XY, Eq. (gXY_ham) with h = 0 (Sec. 3.1): bond weight
+                      exp(beta Delta cos x + beta (1 - Delta) cos 2x) with character
+                      coefficients c_n = sum_m I_{n-2m}(beta Delta) I_m(beta (1 - Delta)),
+                      charges |n| <= n_max */
 } hotrg_model;
 
 typedef enum {
@@ -71,6 +75,18 @@ typedef enum {
   HOTRG_EIG_DENSE = 1  /* always the dense FP64 solver (rocSOLVER dsyevd) */
 } hotrg_eig;
 
+typedef enum {
+  HOTRG_ISO_ONE_SIDED = 0, /* the projector comes from the environment of the left
+                              pair of legs and truncates both pairs (Sec. 2) */
+  HOTRG_ISO_TWO_SIDED = 1  /* original HOTRG: the projectors of the left and of the
+                              right environment are both formed and the one with the
+                              smaller truncation error is used; the right one only
+                              when smaller by more than 1e-12, so reflection-symmetric
+                              models keep the one-sided result.  FP64 contractions
+                              only (HOTRG_ERR_INVALID otherwise); about twice the
+                              environment and eigensolver work */
+} hotrg_isometry;
+
 typedef struct {
   int model;          /* hotrg_model */
   double beta;        /* inverse temperature 1/T (k_B = 1) */
@@ -80,6 +96,8 @@ typedef struct {
   const double* raw;  /* HOTRG_RAW: host array raw_dx*raw_dy*raw_dx*raw_dy,
                          legs (l,u,r,d); copied during the call */
   int raw_dx, raw_dy; /* HOTRG_RAW: left/right and up/down dimensions */
+  double delta;       /* GXY: weight Delta of cos(theta_i - theta_j), 0 <= Delta <= 1
+                         (1 - Delta weighs cos 2(theta_i - theta_j)); ignored otherwise */
 } hotrg_model_params;
 
 typedef struct {
@@ -90,6 +108,7 @@ typedef struct {
   double degen_tol;   /* multiplet tolerance tau (relative to lambda_1) */
   int spec_len;       /* spectrum values recorded per step (0: none) */
   int eig;            /* hotrg_eig: how the leading eigenpairs of M are found */
+  int isometry;       /* hotrg_isometry */
 } hotrg_opts;
 
 typedef struct {
@@ -100,6 +119,7 @@ typedef struct {
   double trunc_err;   /* 1 - sum_{m<=kept} lambda_m / trace(M) */
   double cut_gap;     /* (lambda_{D'} - lambda_{D'+1}) / lambda_1; -1 when nothing is cut */
   double lnz_torus;   /* ln Z / N of the 2^k-site torus after this step */
+  int side;           /* environment the projector came from: 0 left, 1 right */
 } hotrg_step_info;
 
 typedef struct {
@@ -197,6 +217,19 @@ hotrg_status hotrg_footprint(const hotrg_model_params* params, const hotrg_opts*
 hotrg_status hotrg_run_batch(hotrg_ctx* ctx, int n, const hotrg_model_params* params,
                              const hotrg_opts* opts, hotrg_result* results,
                              hotrg_status* statuses);
+
+/* Internal energy and specific heat per site by finite differences of ln Z/N
+ * in beta (Sec. 3.3 obtains the specific heat as a finite-difference second
+ * derivative of ln Z): the problem of `params` / `opts` is run at
+ * beta + j dbeta, j = -2 .. 2, on the context's worker pool, and the
+ * five-point central stencils (error O(dbeta^4)) give
+ *   out[0] = ln Z / N at beta,
+ *   out[1] = u = -d(ln Z/N)/d beta       (energy per site),
+ *   out[2] = c = beta^2 d^2(ln Z/N)/d beta^2   (specific heat per site, k_B = 1).
+ * `out` is caller-owned (3 doubles).  HOTRG_ERR_INVALID for HOTRG_RAW, for
+ * dbeta <= 0 or beta - 2 dbeta < 0; otherwise the first failing run's status. */
+hotrg_status hotrg_thermo(hotrg_ctx* ctx, const hotrg_model_params* params,
+                          const hotrg_opts* opts, double dbeta, double* out);
 /* Serving counters: requests admitted, queue passes where the oldest queued
  * request did not fit, peak bytes reserved by running requests. */
 hotrg_status hotrg_ctx_sched_stats(hotrg_ctx* ctx, uint64_t* admitted, uint64_t* stalls,

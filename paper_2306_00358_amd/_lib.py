@@ -13,20 +13,23 @@ LIB_PATH = os.path.join(_PKG, "libhotrg.so")
 
 HOTRG_OK, HOTRG_ERR_INVALID, HOTRG_ERR_OOM, HOTRG_ERR_DEVICE, HOTRG_ERR_NUMERIC, \
     HOTRG_ERR_NOT_READY, HOTRG_ERR_CANCELLED = range(7)
-HOTRG_ISING, HOTRG_XY, HOTRG_POTTS, HOTRG_RAW = range(4)
+HOTRG_ISING, HOTRG_XY, HOTRG_POTTS, HOTRG_RAW, HOTRG_GXY = range(5)
 HOTRG_FP64, HOTRG_FP32, HOTRG_BF16X3 = range(3)
 HOTRG_TRUNC_PLAIN, HOTRG_TRUNC_MULTIPLET = range(2)
+HOTRG_ISO_ONE_SIDED, HOTRG_ISO_TWO_SIDED = range(2)
 
 PREC = {"fp64": HOTRG_FP64, "fp32": HOTRG_FP32, "bf16x3": HOTRG_BF16X3}
 TRUNC = {"plain": HOTRG_TRUNC_PLAIN, "multiplet": HOTRG_TRUNC_MULTIPLET}
-MODEL = {"ising": HOTRG_ISING, "xy": HOTRG_XY, "potts": HOTRG_POTTS, "raw": HOTRG_RAW}
+MODEL = {"ising": HOTRG_ISING, "xy": HOTRG_XY, "potts": HOTRG_POTTS, "raw": HOTRG_RAW,
+         "gxy": HOTRG_GXY}
+ISOMETRY = {"one": HOTRG_ISO_ONE_SIDED, "two": HOTRG_ISO_TWO_SIDED}
 
 EXPORTS = [
     "hotrg_ctx_create", "hotrg_ctx_destroy", "hotrg_last_error", "hotrg_ctx_bytes_in_use",
     "hotrg_init_tensor", "hotrg_step", "hotrg_finish", "hotrg_state_export", "hotrg_state_free",
     "hotrg_run", "hotrg_environment", "hotrg_coarse", "hotrg_ctx_enable_timing", "hotrg_ctx_timings",
     "hotrg_ctx_set_workers", "hotrg_submit", "hotrg_poll", "hotrg_wait", "hotrg_cancel",
-    "hotrg_footprint", "hotrg_run_batch", "hotrg_ctx_sched_stats",
+    "hotrg_footprint", "hotrg_run_batch", "hotrg_ctx_sched_stats", "hotrg_thermo",
 ]
 
 PHASES = ["env", "eigh", "proj", "c1", "c2", "c3", "norm"]
@@ -40,18 +43,20 @@ class HotrgError(RuntimeError):
 
 class ModelParams(ctypes.Structure):
     _fields_ = [("model", c_int), ("beta", c_double), ("J", c_double), ("n_max", c_int),
-                ("q", c_int), ("raw", POINTER(c_double)), ("raw_dx", c_int), ("raw_dy", c_int)]
+                ("q", c_int), ("raw", POINTER(c_double)), ("raw_dx", c_int), ("raw_dy", c_int),
+                ("delta", c_double)]
 
 
 class Opts(ctypes.Structure):
     _fields_ = [("d_cut", c_int), ("n_steps", c_int), ("prec", c_int), ("trunc", c_int),
-                ("degen_tol", c_double), ("spec_len", c_int), ("eig", c_int)]
+                ("degen_tol", c_double), ("spec_len", c_int), ("eig", c_int),
+                ("isometry", c_int)]
 
 
 class StepInfo(ctypes.Structure):
     _fields_ = [("dx", c_int), ("dy", c_int), ("d_new", c_int), ("kept", c_int),
                 ("log_norm", c_double), ("trunc_err", c_double), ("cut_gap", c_double),
-                ("lnz_torus", c_double)]
+                ("lnz_torus", c_double), ("side", c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -109,6 +114,7 @@ def lib():
     L.hotrg_ctx_sched_stats.argtypes = [vp, POINTER(ctypes.c_uint64), POINTER(ctypes.c_uint64),
                                         POINTER(c_size_t)]
     L.hotrg_ctx_timings.argtypes = [vp, POINTER(PhaseTime), c_int]
+    L.hotrg_thermo.argtypes = [vp, POINTER(ModelParams), POINTER(Opts), c_double, POINTER(c_double)]
     for name in EXPORTS:
         if name not in ("hotrg_ctx_destroy", "hotrg_state_free", "hotrg_last_error",
                         "hotrg_ctx_bytes_in_use"):
@@ -122,11 +128,12 @@ def _check(status):
         raise HotrgError(status, lib().hotrg_last_error().decode())
 
 
-def model_params(model="ising", beta=0.44, J=1.0, n_max=0, q=2, raw=None):
+def model_params(model="ising", beta=0.44, J=1.0, n_max=0, q=2, raw=None, delta=1.0):
     """ModelParams for a named model; `raw` is an array (dx, dy, dx, dy)."""
     p = ModelParams()
     p.model = MODEL[model] if isinstance(model, str) else int(model)
     p.beta, p.J, p.n_max, p.q = float(beta), float(J), int(n_max), int(q)
+    p.delta = float(delta)
     p._keep = None
     if raw is not None:
         a = np.ascontiguousarray(raw, dtype=np.float64)
@@ -142,9 +149,10 @@ EIG = {"auto": 0, "dense": 1}
 
 
 def make_opts(d_cut, n_steps=0, prec="fp64", trunc="plain", degen_tol=1e-10, spec_len=0,
-              eig="auto"):
+              eig="auto", isometry="one"):
     o = Opts()
     o.eig = EIG[eig] if isinstance(eig, str) else int(eig)
+    o.isometry = ISOMETRY[isometry] if isinstance(isometry, str) else int(isometry)
     o.d_cut, o.n_steps = int(d_cut), int(n_steps)
     o.prec = PREC[prec] if isinstance(prec, str) else int(prec)
     o.trunc = TRUNC[trunc] if isinstance(trunc, str) else int(trunc)
@@ -356,3 +364,11 @@ class Ticket:
         if st != HOTRG_OK:
             raise HotrgError(st, lib().hotrg_last_error().decode())
         return _result_dict(self.result, self.infos, self.spec, self.opts.n_steps, self.opts.spec_len)
+
+
+def hotrg_thermo(ctx, params, opts, dbeta):
+    """ln Z/N, energy per site and specific heat per site at params.beta by
+    five-point differences over beta +- dbeta, +- 2 dbeta (hotrg_thermo)."""
+    out = (c_double * 3)()
+    _check(lib().hotrg_thermo(ctx.ptr, byref(params), byref(opts), float(dbeta), out))
+    return {"lnz": out[0], "energy": out[1], "cv": out[2]}

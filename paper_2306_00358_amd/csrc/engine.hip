@@ -29,6 +29,7 @@ namespace hotrg {
 std::vector<double> ising_tensor(double beta, double J);
 std::vector<double> xy_tensor(double beta, int n_max);
 std::vector<double> potts_tensor(double beta, int q);
+std::vector<double> gxy_tensor(double beta, double delta, int n_max);
 }  // namespace hotrg
 
 using namespace hotrg;
@@ -55,6 +56,14 @@ struct Buf {
   size_t bytes = 0;
 };
 
+// doubles per step record: ln n_k, truncation error, cut gap, torus ln Z/N,
+// kept columns, side of the environment the projector came from
+constexpr int kRec = 6;
+
+// two-sided choice: the right projector only when its truncation error is
+// smaller by more than this (reflection-symmetric tensors keep the left one)
+constexpr double kSideMargin = 1e-12;
+
 }  // namespace
 
 struct hotrg_ctx {
@@ -66,6 +75,9 @@ struct hotrg_ctx {
   rocblas_handle blas = nullptr;
   // step workspace, grown on demand
   Buf A1, A2, M, W, E, Ucan, U1, U3, X1, X2, Tt, scal, EW, Xr;
+  // two-sided isometry: mirrored operands, right environment and its solve,
+  // and its step record / kept count / trace / spectrum (Side)
+  Buf Tm, Xm, M2, W2, Xr2, Side;
   // reduced-precision workspace: [0] hi / float, [1] lo (split bf16 only)
   Buf RA1[2], RA2[2], RX1[2], RX2[2], RU1[2], RU3[2];
   // scal layout (bytes): 0 maxbits (u64), 8 info (int), 16 kept (int), 24 finish out (double),
@@ -99,11 +111,12 @@ struct hotrg_state {
   Buf Tn, Xt, Tp;      // FP64 operands of the next step (normalised)
   Buf RO[4][2];        // reduced-precision operands OT, OX, OC1, OC2 ([.][0] hi/float, [.][1] lo)
   Buf acc;             // device double: ln n_0 + sum_k 2^-k ln n_k
-  Buf recs;            // device: 5 doubles per step
+  Buf recs;            // device: kRec doubles per step
   Buf spec;            // device spectra, spec_cap doubles per step
   int rec_cap = 0, spec_len = 0;
   // sweeps the last iterative eigensolve of each step parity needed, and its n
-  int eig_sweeps[2] = {0, 0}, eig_n[2] = {0, 0};
+  // ([parity + 2 * side])
+  int eig_sweeps[4] = {0, 0, 0, 0}, eig_n[4] = {0, 0, 0, 0};
 };
 
 namespace {
@@ -202,7 +215,11 @@ void check_opts(const hotrg_opts* o) {
   if (o->spec_len < 0) fail(HOTRG_ERR_INVALID, "spec_len must be >= 0");
   if (o->eig != HOTRG_EIG_AUTO && o->eig != HOTRG_EIG_DENSE)
     fail(HOTRG_ERR_INVALID, "eig must be HOTRG_EIG_AUTO or HOTRG_EIG_DENSE");
+  if (o->isometry != HOTRG_ISO_ONE_SIDED && o->isometry != HOTRG_ISO_TWO_SIDED)
+    fail(HOTRG_ERR_INVALID, "isometry must be HOTRG_ISO_ONE_SIDED or HOTRG_ISO_TWO_SIDED");
   check_prec(o->prec);
+  if (o->isometry == HOTRG_ISO_TWO_SIDED && o->prec != HOTRG_FP64)
+    fail(HOTRG_ERR_INVALID, "two-sided isometry needs FP64 contractions");
 }
 
 // Largest intermediate of a step with dims (dx, dy) and D' = dn, in elements.
@@ -217,13 +234,15 @@ void check_dims(int dx, int dy, int dn) {
 }
 
 // FP64 operands of T (dims dx, dy) in the state: environment halves into M.
-void environment_f64(hotrg_ctx* c, const double* Tn, const double* Xt, int dx, int dy) {
+void environment_f64(hotrg_ctx* c, const double* Tn, const double* Xt, int dx, int dy,
+                     Buf* out = nullptr) {
+  Buf& Mb = out ? *out : c->M;
   const long long P = (long long)dx * dy;  // rows / cols of the halves
   const long long n = (long long)dx * dx;
   const long long K2 = (long long)dy * dy;
   ensure(c, c->A1, (size_t)(P * P) * 8);
   ensure(c, c->A2, (size_t)(P * P) * 8);
-  ensure(c, c->M, (size_t)(n * n) * 8);
+  ensure(c, Mb, (size_t)(n * n) * 8);
   // A2[(i,e),(k,f)] = sum_{c,d} T[i,e,c,d] T[k,f,c,d], stored as A2'[(i,k),(e,f)]
   // rows (i,e): i -> dx*dy^2, e -> dy; cols (k,f): k -> dy^2, f -> 1
   const OutMap o2 = omap2(dy, dx * K2, dy, dy, K2, 1);
@@ -235,7 +254,7 @@ void environment_f64(hotrg_ctx* c, const double* Tn, const double* Xt, int dx, i
   // M[(i,j),(k,l)] = sum_{e,f} A2'[(i,k),(e,f)] A1'[(j,l),(e,f)]: GEMM rows (i,k), cols (j,l)
   // rows (i,k): i -> dx*n, k -> dx; cols (j,l): j -> n, l -> 1
   const OutMap om = omap2(dx, dx * n, dx, dx, n, 1);
-  gemm_f64((const double*)c->A2.p, K2, (const double*)c->A1.p, K2, B_KCONTIG, (double*)c->M.p, om,
+  gemm_f64((const double*)c->A2.p, K2, (const double*)c->A1.p, K2, B_KCONTIG, (double*)Mb.p, om,
            (int)n, (int)n, (int)K2, nullptr, c->stream, GEMM_TAG_ENV);
 }
 
@@ -440,7 +459,7 @@ void do_step(hotrg_ctx* c, hotrg_state* st, const hotrg_opts* o) {
   if (k > st->rec_cap) {
     int cap = st->rec_cap ? 2 * st->rec_cap : 64;
     while (cap < k) cap *= 2;
-    ensure_keep(c, st->recs, (size_t)cap * 5 * 8, (size_t)st->rec_cap * 5 * 8);
+    ensure_keep(c, st->recs, (size_t)cap * kRec * 8, (size_t)st->rec_cap * kRec * 8);
     if (st->spec_len)
       ensure_keep(c, st->spec, (size_t)cap * st->spec_len * 8, (size_t)st->rec_cap * st->spec_len * 8);
     st->rec_cap = cap;
@@ -451,7 +470,7 @@ void do_step(hotrg_ctx* c, hotrg_state* st, const hotrg_opts* o) {
     st->spec_len = o->spec_len;
     if (st->spec_len) ensure(c, st->spec, (size_t)st->rec_cap * st->spec_len * 8);
   }
-  double* rec = (double*)st->recs.p + 5 * (size_t)(k - 1);
+  double* rec = (double*)st->recs.p + kRec * (size_t)(k - 1);
   double* spec = st->spec_len ? (double*)st->spec.p + (size_t)(k - 1) * st->spec_len : nullptr;
   ensure(c, c->scal, 64);
   unsigned long long* mb = (unsigned long long*)c->scal.p;
@@ -487,7 +506,6 @@ void do_step(hotrg_ctx* c, hotrg_state* st, const hotrg_opts* o) {
     environment_rp(c, st, rp_mode(sp), dx, dy);
   launch_symmetrize((double*)c->M.p, n, c->stream);
   // FP64 eigendecomposition, spectrum and projector
-  ensure(c, c->W, (size_t)n * 8);
   ensure(c, c->E, (size_t)n * 8);
   double* trace = (double*)((char*)c->scal.p + 40);
   launch_trace((const double*)c->M.p, n, trace, c->stream);
@@ -496,42 +514,89 @@ void do_step(hotrg_ctx* c, hotrg_state* st, const hotrg_opts* o) {
   const int need = std::max(dn + 1, std::min(o->spec_len, n));
   int p = std::min(128, std::max(2 * dn, need + 16));
   p = (p + 15) / 16 * 16;
-  bool sub = o->eig == HOTRG_EIG_AUTO && n >= 1024 && need + 16 <= p && p <= 128 && p * 4 <= n;
-  const double* evec = nullptr;
-  int cols = n;
-  if (sub) {
-    ensure(c, c->EW, topk_workspace_doubles(n, p) * 8);
-    ensure(c, c->Xr, (size_t)p * n * 8);
-    int iters = 0;
-    double resid = 0.0;
-    // steps of equal parity see environments of the same kind: start with
-    // one sweep more than the last such solve needed
-    const int par = st->k & 1;
-    const int q_first = st->eig_n[par] == n ? st->eig_sweeps[par] + 1 : 3;
-    sub = topk_eigs(c->blas, (const double*)c->M.p, n, p, need, 5e-14, q_first,
-                    (double*)c->EW.p, (double*)c->W.p, (double*)c->Xr.p,
-                    (int*)((char*)c->scal.p + 48), &iters, &resid, c->stream);
-    st->eig_n[par] = sub ? n : 0;
-    st->eig_sweeps[par] = iters;
-    c->last_eig_iters = sub ? iters : 0;
-    c->last_eig_resid = resid;
+  const bool sub_ok = o->eig == HOTRG_EIG_AUTO && n >= 1024 && need + 16 <= p && p <= 128 &&
+                      p * 4 <= n;
+  // eigenpairs of Mb into Wb (and Xb or Mb itself); returns the eigenvector
+  // rows and their count
+  auto solve = [&](Buf& Mb, Buf& Wb, Buf& Xb, int side, int* inf, int* cols_out) {
+    ensure(c, Wb, (size_t)n * 8);
+    bool sub = sub_ok;
     if (sub) {
-      evec = (const double*)c->Xr.p;
-      cols = p;
+      ensure(c, c->EW, topk_workspace_doubles(n, p) * 8);
+      ensure(c, Xb, (size_t)p * n * 8);
+      int iters = 0;
+      double resid = 0.0;
+      // steps of equal parity see environments of the same kind: start with
+      // one sweep more than the last such solve needed
+      const int slot = (st->k & 1) + 2 * side;
+      const int q_first = st->eig_n[slot] == n ? st->eig_sweeps[slot] + 1 : 3;
+      sub = topk_eigs(c->blas, (const double*)Mb.p, n, p, need, 5e-14, q_first,
+                      (double*)c->EW.p, (double*)Wb.p, (double*)Xb.p,
+                      (int*)((char*)c->scal.p + 48), &iters, &resid, c->stream);
+      st->eig_n[slot] = sub ? n : 0;
+      st->eig_sweeps[slot] = iters;
+      c->last_eig_iters = sub ? iters : 0;
+      c->last_eig_resid = resid;
+      if (sub) {
+        *cols_out = p;
+        return (const double*)Xb.p;
+      }
     }
-  }
-  if (!sub) {
     rocblas_status rs = rocsolver_dsyevd(c->blas, rocblas_evect_original, rocblas_fill_lower, n,
-                                         (double*)c->M.p, n, (double*)c->W.p, (double*)c->E.p,
-                                         info);
+                                         (double*)Mb.p, n, (double*)Wb.p, (double*)c->E.p, inf);
     if (rs != rocblas_status_success)
       fail(HOTRG_ERR_DEVICE, "rocsolver_dsyevd failed with status " + std::to_string((int)rs));
-    evec = (const double*)c->M.p;
-    cols = n;
-  }
+    *cols_out = n;
+    return (const double*)Mb.p;
+  };
+  int cols = n;
+  const double* evec = solve(c->M, c->W, c->Xr, 0, info, &cols);
   mark(c, HOTRG_PHASE_PROJ);
   launch_spectrum((const double*)c->W.p, cols, n, dn, o->trunc, o->degen_tol, st->spec_len,
                   trace, spec, rec, kept, c->stream);
+  launch_store(rec + 5, 0.0, c->stream);
+  if (o->isometry == HOTRG_ISO_TWO_SIDED && dn < n) {
+    // the right pair of legs: environment of the reflected tensor (FP64)
+    if (sp != HOTRG_FP64) fail(HOTRG_ERR_INVALID, "two-sided isometry needs FP64 contractions");
+    const size_t ne = (size_t)dx * dy * dx * dy;
+    ensure(c, c->Tm, ne * 8);
+    ensure(c, c->Xm, ne * 8);
+    ensure(c, c->Side, (size_t)(kRec + 3 + st->spec_len) * 8);
+    double* rec2 = (double*)c->Side.p;
+    int* kept2 = (int*)(rec2 + kRec);
+    double* trace2 = rec2 + kRec + 1;
+    int* info2 = (int*)(rec2 + kRec + 2);
+    double* spec2 = st->spec_len ? rec2 + kRec + 3 : nullptr;
+    mark(c, HOTRG_PHASE_ENV);
+    launch_prep_mirror((const double*)st->Tn.p, dx, dy, (double*)c->Tm.p, (double*)c->Xm.p,
+                       c->stream);
+    environment_f64(c, (const double*)c->Tm.p, (const double*)c->Xm.p, dx, dy, &c->M2);
+    launch_symmetrize((double*)c->M2.p, n, c->stream);
+    launch_trace((const double*)c->M2.p, n, trace2, c->stream);
+    mark(c, HOTRG_PHASE_EIGH);
+    int cols2 = n;
+    const double* evec2 = solve(c->M2, c->W2, c->Xr2, 1, info2, &cols2);
+    mark(c, HOTRG_PHASE_PROJ);
+    launch_spectrum((const double*)c->W2.p, cols2, n, dn, o->trunc, o->degen_tol, st->spec_len,
+                    trace2, spec2, rec2, kept2, c->stream);
+    double errs[2] = {0.0, 0.0};
+    int inf2 = 0;
+    HIPCHK(hipMemcpyAsync(&errs[0], rec + 1, 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(&errs[1], rec2 + 1, 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(&inf2, info2, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (inf2 != 0) fail(HOTRG_ERR_NUMERIC, "eigensolver did not converge (right environment)");
+    if (errs[1] < errs[0] - kSideMargin) {
+      HIPCHK(hipMemcpyAsync(rec, rec2, 5 * 8, hipMemcpyDeviceToDevice, c->stream));
+      HIPCHK(hipMemcpyAsync(kept, kept2, sizeof(int), hipMemcpyDeviceToDevice, c->stream));
+      if (spec)
+        HIPCHK(hipMemcpyAsync(spec, spec2, (size_t)st->spec_len * 8, hipMemcpyDeviceToDevice,
+                              c->stream));
+      launch_store(rec + 5, 1.0, c->stream);
+      evec = evec2;
+      cols = cols2;
+    }
+  }
   ensure(c, c->Ucan, (size_t)n * dn * 8);
   launch_isometry(evec, cols, n, dn, kept, (double*)c->Ucan.p, c->stream);
   if (sp == HOTRG_FP64) {
@@ -573,9 +638,9 @@ void do_step(hotrg_ctx* c, hotrg_state* st, const hotrg_opts* o) {
 void fetch_info(hotrg_ctx* c, hotrg_state* st, int first, int count, const int* dims_dx,
                 hotrg_step_info* out, double* spectra) {
   // dims are reconstructed by the caller; records come from the device
-  std::vector<double> r((size_t)count * 5);
+  std::vector<double> r((size_t)count * kRec);
   if (count == 0) return;
-  HIPCHK(hipMemcpyAsync(r.data(), (double*)st->recs.p + 5 * (size_t)first, r.size() * 8,
+  HIPCHK(hipMemcpyAsync(r.data(), (double*)st->recs.p + kRec * (size_t)first, r.size() * 8,
                         hipMemcpyDeviceToHost, c->stream));
   if (spectra && st->spec_len)
     HIPCHK(hipMemcpyAsync(spectra, (double*)st->spec.p + (size_t)first * st->spec_len,
@@ -583,11 +648,12 @@ void fetch_info(hotrg_ctx* c, hotrg_state* st, int first, int count, const int* 
   HIPCHK(hipStreamSynchronize(c->stream));
   if (out)
     for (int i = 0; i < count; ++i) {
-      out[i].log_norm = r[5 * i + 0];
-      out[i].trunc_err = r[5 * i + 1];
-      out[i].cut_gap = r[5 * i + 2];
-      out[i].lnz_torus = r[5 * i + 3];
-      out[i].kept = (int)r[5 * i + 4];
+      out[i].log_norm = r[kRec * i + 0];
+      out[i].trunc_err = r[kRec * i + 1];
+      out[i].cut_gap = r[kRec * i + 2];
+      out[i].lnz_torus = r[kRec * i + 3];
+      out[i].kept = (int)r[kRec * i + 4];
+      out[i].side = (int)r[kRec * i + 5];
     }
   (void)dims_dx;
 }
@@ -612,6 +678,9 @@ std::vector<double> build_tensor(const hotrg_model_params* p, int* dx, int* dy) 
       case HOTRG_POTTS:
         *dx = *dy = p->q;
         return potts_tensor(p->beta, p->q);
+      case HOTRG_GXY:
+        *dx = *dy = 2 * p->n_max + 1;
+        return gxy_tensor(p->beta, p->delta, p->n_max);
       case HOTRG_RAW: {
         if (!p->raw || p->raw_dx < 1 || p->raw_dy < 1 || p->raw_dx > 128 || p->raw_dy > 16384)
           fail(HOTRG_ERR_INVALID, "raw tensor: need raw != NULL, 1 <= raw_dx <= 128, raw_dy >= 1");
@@ -693,7 +762,8 @@ void ctx_trim(hotrg_ctx* c) {
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
   Buf* bufs[] = {&c->A1, &c->A2, &c->M, &c->W, &c->E, &c->Ucan, &c->U1, &c->U3,
-                 &c->X1, &c->X2, &c->Tt, &c->EW, &c->Xr};
+                 &c->X1, &c->X2, &c->Tt, &c->EW, &c->Xr, &c->Tm, &c->Xm, &c->M2,
+                 &c->W2, &c->Xr2, &c->Side};
   for (Buf* b : bufs) ctx_free(c, *b);
   for (Buf* arr : {c->RA1, c->RA2, c->RX1, c->RX2, c->RU1, c->RU3})
     for (int h = 0; h < 2; ++h) ctx_free(c, arr[h]);
@@ -752,7 +822,8 @@ void hotrg_ctx_destroy(hotrg_ctx* c) {
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
   Buf* bufs[] = {&c->A1, &c->A2, &c->M, &c->W, &c->E, &c->Ucan, &c->U1, &c->U3,
-                 &c->X1, &c->X2, &c->Tt, &c->scal, &c->EW, &c->Xr};
+                 &c->X1, &c->X2, &c->Tt, &c->scal, &c->EW, &c->Xr, &c->Tm, &c->Xm,
+                 &c->M2, &c->W2, &c->Xr2, &c->Side};
   for (Buf* b : bufs) ctx_free(c, *b);
   for (Buf* arr : {c->RA1, c->RA2, c->RX1, c->RX2, c->RU1, c->RU3})
     for (int h = 0; h < 2; ++h) ctx_free(c, arr[h]);
@@ -787,6 +858,8 @@ hotrg_status hotrg_step(hotrg_ctx* c, hotrg_state* st, const hotrg_opts* o, hotr
   return guard([&] {
     if (!c || !st) fail(HOTRG_ERR_INVALID, "ctx/state is NULL");
     check_opts(o);
+    if (o->isometry == HOTRG_ISO_TWO_SIDED && st->prec != HOTRG_FP64)
+      fail(HOTRG_ERR_INVALID, "two-sided isometry needs FP64 contractions");
     HIPCHK(hipSetDevice(c->device));
     const int dx = st->dx, dy = st->dy;
     do_step(c, st, o);

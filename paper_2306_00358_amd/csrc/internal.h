@@ -106,6 +106,8 @@ void launch_init_acc(const unsigned long long* maxbits, double* acc, hipStream_t
 // optionally with legs transposed (l,u,r,d) -> (u,l,d,r), scaled by
 // 1/max (read from maxbits): Tn natural (dx,dy,dx,dy); Xt [(l,d),(u,r)];
 // Tp [(l,u),(d,r)].  Outputs are f64 or f32 per out_f32.
+void launch_prep_mirror(const double* T, int dx, int dy, double* Tn, double* Xt, hipStream_t s);
+void launch_store(double* p, double v, hipStream_t s);
 void launch_prep(const void* src, bool src_f32, bool rotate, int dx, int dy,
                  const unsigned long long* maxbits, void* Tn, void* Xt, void* Tp, bool out_f32,
                  hipStream_t s);

@@ -81,6 +81,38 @@ void launch_prep(const void* src, bool src_f32, bool rotate, int dx, int dy,
                      dy, maxbits, Tn, Xt, Tp, out_f32);
 }
 
+// The reflected tensor T'[l,u,r,d] = T[r,u,l,d] (FP64, dims (dx,dy,dx,dy)) in
+// the natural layout and in the Xt layout [(l,d),(u,r)]: the operands whose
+// environment is that of the right pair of legs of T.
+__global__ void k_prep_mirror(const double* __restrict__ T, int dx, int dy, double* Tn,
+                              double* Xt) {
+  const long long total = (long long)dx * dy * dx * dy;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    long long q = e;
+    int d = (int)(q % dy); q /= dy;
+    int r = (int)(q % dx); q /= dx;
+    int u = (int)(q % dy); q /= dy;
+    int l = (int)q;
+    const double v = T[(((long long)r * dy + u) * dx + l) * dy + d];
+    Tn[e] = v;
+    Xt[(((long long)l * dy + d) * dy + u) * dx + r] = v;
+  }
+}
+
+void launch_prep_mirror(const double* T, int dx, int dy, double* Tn, double* Xt, hipStream_t s) {
+  long long total = (long long)dx * dy * dx * dy;
+  hipLaunchKernelGGL(k_prep_mirror, dim3(nblocks(total, 256)), dim3(256), 0, s, T, dx, dy, Tn, Xt);
+}
+
+__global__ void k_store(double* p, double v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+void launch_store(double* p, double v, hipStream_t s) {
+  hipLaunchKernelGGL(k_store, dim3(1), dim3(64), 0, s, p, v);
+}
+
 // ------------------------------------------------------------ environment --
 __global__ void k_symmetrize(double* M, int n) {
   long long total = (long long)n * n;

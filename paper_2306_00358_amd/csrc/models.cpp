@@ -46,6 +46,36 @@ std::vector<double> xy_tensor(double beta, int n_max) {
   return T;
 }
 
+// Generalized XY (Sec. 3.1, Eq. (gXY_ham) with h = 0): the bond weight
+// exp(x cos t + y cos 2t), x = beta Delta, y = beta (1 - Delta), has character
+// coefficients c_n = sum_m I_{n-2m}(x) I_m(y) (product of the two expansions);
+// the tensor is the XY construction with I_n replaced by c_n.  The terms fall
+// off like (x/2)^|k| / |k|! (y/2)^|m| / |m|!, so |m| <= n_max + 40 suffices.
+std::vector<double> gxy_tensor(double beta, double delta, int n_max) {
+  if (n_max < 0 || n_max > 64) throw std::invalid_argument("gxy: 0 <= n_max <= 64");
+  if (!(beta >= 0.0)) throw std::invalid_argument("gxy: beta must be >= 0");
+  if (!(delta >= 0.0 && delta <= 1.0)) throw std::invalid_argument("gxy: 0 <= delta <= 1");
+  const double x = beta * delta, y = beta * (1.0 - delta);
+  const int D = 2 * n_max + 1, mm = n_max + 40;
+  std::vector<double> w(D);
+  for (int i = 0; i < D; ++i) {
+    const int n = i - n_max;
+    double c = 0.0;
+    for (int m = -mm; m <= mm; ++m)
+      c += std::cyl_bessel_i((double)std::abs(n - 2 * m), x) *
+           std::cyl_bessel_i((double)std::abs(m), y);
+    w[i] = std::sqrt(c);
+  }
+  std::vector<double> T((size_t)D * D * D * D, 0.0);
+  for (int a = 0; a < D; ++a)
+    for (int b = 0; b < D; ++b)
+      for (int c = 0; c < D; ++c) {
+        int d = a + b - c;
+        if (d >= 0 && d < D) T[(((size_t)a * D + b) * D + c) * D + d] = w[a] * w[b] * w[c] * w[d];
+      }
+  return T;
+}
+
 // q-state Potts (Sec. 3.3): W[a][b] = e^beta if a == b else 1, W = L L^T
 // (Cholesky), T[i,j,k,l] = sum_s L[s][i] L[s][j] L[s][k] L[s][l].
 std::vector<double> potts_tensor(double beta, int q) {

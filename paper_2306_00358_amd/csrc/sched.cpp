@@ -92,6 +92,9 @@ bool initial_dims(const hotrg_model_params* p, int* dx, int* dy) {
     case HOTRG_POTTS:
       *dx = *dy = p->q;
       return p->q >= 2;
+    case HOTRG_GXY:
+      *dx = *dy = 2 * p->n_max + 1;
+      return p->n_max >= 0;
     case HOTRG_RAW:
       *dx = p->raw_dx;
       *dy = p->raw_dy;
@@ -122,6 +125,10 @@ size_t footprint_of(const hotrg_model_params* p, const hotrg_opts* o) {
     const int p = std::min(128, std::max(2 * dn, dn + 17));
     need("eig", (double)topk_workspace_doubles((int)n, (p + 15) / 16 * 16) * 8 + (double)p * n * 8);
     need("dense", n >= 1024 ? n * n * 8 : 0);  // dsyevd fallback workspace
+    if (o->isometry == HOTRG_ISO_TWO_SIDED && dn < n) {
+      // mirrored operands, right environment, its eigenpairs
+      need("side", 2.0 * dx * dy * dx * dy * 8 + n * n * 8 + n * 8 + (double)p * n * 8);
+    }
     if (!red) {
       need("A12", 2 * P * P * 8);
       need("X12", 2 * X * 8);
@@ -170,13 +177,17 @@ void worker_loop(Server* S, int w) {
         auto pick = S->queue.end();
         for (auto it = S->queue.begin(); it != S->queue.end(); ++it) {
           const size_t f = (*it)->footprint;
-          if (others + hold + f <= S->budget || others + f <= S->budget) {
+          if (others + hold + f <= S->budget) {
             pick = it;
-            release = others + hold + f > S->budget;
+            break;
+          }
+          if (others + f <= S->budget) {
+            release = true;  // fits once this worker's buffers are released: release, then pick again
             break;
           }
           if (it == S->queue.begin() && (*it)->skips >= kMaxSkips) break;
         }
+        if (release) break;
         if (pick != S->queue.end()) {
           if (pick != S->queue.begin()) {
             ++S->queue.front()->skips;
@@ -482,6 +493,44 @@ hotrg_status hotrg_run_batch(hotrg_ctx* ctx, int n, const hotrg_model_params* pa
   }
   if (first != HOTRG_OK) set_last_error(first_err.c_str());
   return first;
+}
+
+hotrg_status hotrg_thermo(hotrg_ctx* ctx, const hotrg_model_params* params,
+                          const hotrg_opts* opts, double dbeta, double* out) {
+  if (!ctx || !params || !opts || !out) {
+    set_last_error("NULL argument");
+    return HOTRG_ERR_INVALID;
+  }
+  if (params->model == HOTRG_RAW) {
+    set_last_error("thermo needs a model whose tensor depends on beta");
+    return HOTRG_ERR_INVALID;
+  }
+  if (!(dbeta > 0.0) || !(params->beta - 2.0 * dbeta >= 0.0)) {
+    set_last_error("need dbeta > 0 and beta - 2 dbeta >= 0");
+    return HOTRG_ERR_INVALID;
+  }
+  // ln Z/N at beta + j dbeta, j = -2 .. 2, on the worker pool
+  hotrg_model_params P[5];
+  hotrg_opts O[5];
+  hotrg_result R[5];
+  hotrg_status S[5];
+  for (int j = 0; j < 5; ++j) {
+    P[j] = *params;
+    P[j].beta = params->beta + (j - 2) * dbeta;
+    O[j] = *opts;
+    std::memset(&R[j], 0, sizeof(hotrg_result));
+  }
+  const hotrg_status st = hotrg_run_batch(ctx, 5, P, O, R, S);
+  if (st != HOTRG_OK) return st;
+  double f[5];
+  for (int j = 0; j < 5; ++j) f[j] = R[j].lnz_per_site;
+  // five-point central differences, error O(dbeta^4)
+  const double d1 = (f[0] - 8.0 * f[1] + 8.0 * f[3] - f[4]) / (12.0 * dbeta);
+  const double d2 = (-f[0] + 16.0 * f[1] - 30.0 * f[2] + 16.0 * f[3] - f[4]) / (12.0 * dbeta * dbeta);
+  out[0] = f[2];
+  out[1] = -d1;
+  out[2] = params->beta * params->beta * d2;
+  return HOTRG_OK;
 }
 
 hotrg_status hotrg_ctx_sched_stats(hotrg_ctx* ctx, uint64_t* admitted, uint64_t* stalls,

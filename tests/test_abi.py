@@ -44,10 +44,10 @@ def test_struct_layouts_match_header():
     # field order and sizes of the ctypes mirrors against the C declarations
     from paper_2306_00358_amd import _lib
 
-    assert ctypes.sizeof(_lib.StepInfo) == 4 * 4 + 4 * 8
-    assert ctypes.sizeof(_lib.Opts) == 4 * 4 + 8 + 8  # 4 ints, double, 2 ints
+    assert ctypes.sizeof(_lib.StepInfo) == 4 * 4 + 4 * 8 + 8  # side, padded
+    assert ctypes.sizeof(_lib.Opts) == 4 * 4 + 8 + 3 * 4 + 4  # 4 ints, double, 3 ints, pad
     assert [f for f, _ in _lib.ModelParams._fields_] == [
-        "model", "beta", "J", "n_max", "q", "raw", "raw_dx", "raw_dy"]
+        "model", "beta", "J", "n_max", "q", "raw", "raw_dx", "raw_dy", "delta"]
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
@@ -81,3 +81,34 @@ def test_footprint_host_estimate():
     # the two D^5 intermediates dominate: 2 * 64^5 * 8 bytes at D = 64
     assert 2 * 64**5 * 8 < f64 < 4 * 64**5 * 8
     assert hotrg_footprint(p, make_opts(64, 30, prec="fp32")) < f64
+
+
+def test_struct_offsets_match_the_c_compiler(tmp_path):
+    # offsetof / sizeof of every field as gcc lays out include/hotrg.h,
+    # against the ctypes mirrors of the binding
+    import shutil
+    import subprocess
+
+    from paper_2306_00358_amd import _lib
+
+    if not shutil.which("gcc"):
+        pytest.skip("gcc not available")
+    structs = {"hotrg_model_params": _lib.ModelParams, "hotrg_opts": _lib.Opts,
+               "hotrg_step_info": _lib.StepInfo, "hotrg_result": _lib.Result}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "hotrg.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append('printf("%s sizeof %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f, _ in py._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, f))
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(line.split()[:2]): int(line.split()[2]) for line in out if line}
+    for cname, py in structs.items():
+        assert got[(cname, "sizeof")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
