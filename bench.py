@@ -59,7 +59,7 @@ def parse():
                     help="serve a seeded Poisson stream of N mixed requests instead")
     ap.add_argument("--no-serve-check", dest="serve_check", action="store_false",
                     help="skip the FP64 re-run of every served request")
-    ap.add_argument("--workers", type=int, default=4)
+    ap.add_argument("--workers", type=int, default=8)
     ap.add_argument("--kernel-probe", action="store_true",
                     help="run one coarse contraction at the benchmark shape and a 1 GiB "
                          "calibration copy (for hardware-counter runs), then exit")

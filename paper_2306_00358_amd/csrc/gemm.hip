@@ -368,10 +368,13 @@ void gemm_f64(const double* A, long long lda, const double* B, long long ldb, in
               hipStream_t s, int tag) {
   if (M <= 0 || N <= 0) return;
   // kernel choice for large products: HOTRG_GEMM_VARIANT (tuning only)
-  static const int variant = [] {
+  static const int forced = [] {
     const char* e = std::getenv("HOTRG_GEMM_VARIANT");
-    return e ? std::atoi(e) : 1;
+    return e ? std::atoi(e) : -1;
   }();
+  // default: 256 x 128 tiles, three LDS stages for long K (one barrier per
+  // slab, two slabs in flight), two for short K
+  const int variant = forced >= 0 ? forced : (K >= 256 ? 3 : 1);
   if ((long long)M * N >= (1LL << 20) && N >= 128 && variant != 2 &&
       gemm_f64_lds(A, lda, B, ldb, blayout, C, om, M, N, K, maxbits, s, tag, variant))
     return;

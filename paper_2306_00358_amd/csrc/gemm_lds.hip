@@ -7,8 +7,11 @@
 //
 // Block: WGM x WGN waves, each owning a 64 x 64 output tile of 4 x 4
 // v_mfma_f64_16x16x4f64 tiles (accumulators stay in registers for the whole
-// K loop).  K advances in slabs of BK; two LDS stages: the slab s+1 copy is
-// in flight while slab s is multiplied.
+// K loop).  K advances in slabs of BK through NST LDS stages.  Two stages:
+// the slab s+1 copy is in flight while slab s is multiplied, with a barrier
+// after the copy lands and one before the stage is refilled.  Three stages:
+// slabs s+1 and s+2 are in flight; one barrier per slab both publishes slab
+// s and frees the stage of slab s-1 for the copy of slab s+2.
 //
 // LDS layout.  Operand rows that are K-contiguous in global memory (A, and B
 // when K-contiguous) are stored as rows of BK doubles cut into 16-byte
@@ -97,7 +100,7 @@ __device__ __forceinline__ void load_ncontig(const double* __restrict__ G, long 
   }
 }
 
-template <int WGM, int WGN, int BK, int BL, int TAG>
+template <int WGM, int WGN, int BK, int BL, int TAG, int NST>
 __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm_f64_lds(
     const double* __restrict__ A, long long lda, const double* __restrict__ B, long long ldb,
     double* __restrict__ C, OutMap om, int M, int N, int K, unsigned long long* maxbits) {
@@ -111,7 +114,8 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm_f64_lds(
   constexpr int B_INST = BL == B_NCONTIG ? BK / NW : BN / (1024 / (BK * 8)) / NW;
   constexpr int LOADS = A_INST + B_INST;  // global_load_lds per wave per slab
   static_assert(LOADS <= 63, "vmcnt range");
-  __shared__ __attribute__((aligned(16))) char smem[2 * STAGE];
+  static_assert(NST == 2 || NST == 3, "two or three LDS stages");
+  __shared__ __attribute__((aligned(16))) char smem[NST * STAGE];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -137,19 +141,30 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm_f64_lds(
 
   const int nslab = K / BK;
   issue(0, 0);
+  if (NST == 3 && nslab > 1) issue(BK, 1);
   for (int s = 0; s < nslab; ++s) {
-    const int cur = s & 1;
-    if (s + 1 < nslab) {
-      issue((s + 1) * BK, cur ^ 1);
-      // this wave's copies of slab s are done; those of slab s+1 may be pending
-      asm volatile("s_waitcnt vmcnt(%0)" ::"n"(LOADS) : "memory");
+    const int cur = NST == 2 ? (s & 1) : s % 3;
+    if (NST == 2) {
+      if (s + 1 < nslab) {
+        issue((s + 1) * BK, cur ^ 1);
+        // this wave's copies of slab s are done; those of slab s+1 may be pending
+        asm volatile("s_waitcnt vmcnt(%0)" ::"n"(LOADS) : "memory");
+      } else {
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      }
     } else {
-      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      // slabs s and s+1 are in flight: wait for s only
+      if (s + 1 < nslab)
+        asm volatile("s_waitcnt vmcnt(%0)" ::"n"(LOADS) : "memory");
+      else
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     }
     // every wave's copies of slab s have landed (a plain barrier: a fenced
-    // one would also wait for the slab s+1 copies still in flight)
+    // one would also wait for the copies still in flight); with three stages
+    // every wave has also finished reading slab s-1, whose stage takes s+2
     __builtin_amdgcn_s_barrier();
-    asm volatile("" ::: "memory");  // no LDS read moves above the barrier
+    asm volatile("" ::: "memory");  // no LDS access moves above the barrier
+    if (NST == 3 && s + 2 < nslab) issue((s + 2) * BK, (s + 2) % 3);
     const char* as = smem + cur * STAGE;
     const char* bs = as + A_BYTES;
     // A values of this lane for the slab: rows wm*64 + i*16 + li, k in [lg*KQ, lg*KQ + KQ)
@@ -201,8 +216,10 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm_f64_lds(
     }
     // all LDS reads of this stage have returned before any wave refills it
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-    __builtin_amdgcn_s_barrier();
-    asm volatile("" ::: "memory");  // no copy into the stage moves above the barrier
+    if (NST == 2) {
+      __builtin_amdgcn_s_barrier();
+      asm volatile("" ::: "memory");  // no copy into the stage moves above the barrier
+    }
   }
 
   double mx = 0.0;
@@ -236,7 +253,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm_f64_lds(
   }
 }
 
-template <int WGM, int WGN, int BK, int TAG>
+template <int WGM, int WGN, int BK, int TAG, int NST = 2>
 static void launch_lds(const double* A, long long lda, const double* B, long long ldb, int bl,
                        double* C, const OutMap& om, int M, int N, int K,
                        unsigned long long* maxbits, hipStream_t s) {
@@ -244,24 +261,31 @@ static void launch_lds(const double* A, long long lda, const double* B, long lon
   dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM);
   dim3 block(64 * WGM * WGN);
   if (bl == B_NCONTIG)
-    hipLaunchKernelGGL((k_gemm_f64_lds<WGM, WGN, BK, B_NCONTIG, TAG>), grid, block, 0, s, A, lda, B,
-                       ldb, C, om, M, N, K, maxbits);
+    hipLaunchKernelGGL((k_gemm_f64_lds<WGM, WGN, BK, B_NCONTIG, TAG, NST>), grid, block, 0, s, A,
+                       lda, B, ldb, C, om, M, N, K, maxbits);
   else
-    hipLaunchKernelGGL((k_gemm_f64_lds<WGM, WGN, BK, B_KCONTIG, TAG>), grid, block, 0, s, A, lda, B,
-                       ldb, C, om, M, N, K, maxbits);
+    hipLaunchKernelGGL((k_gemm_f64_lds<WGM, WGN, BK, B_KCONTIG, TAG, NST>), grid, block, 0, s, A,
+                       lda, B, ldb, C, om, M, N, K, maxbits);
 }
 
 // Returns false when the operands do not meet the requirements above.
 bool gemm_f64_lds(const double* A, long long lda, const double* B, long long ldb, int blayout,
                   double* C, const OutMap& om, int M, int N, int K, unsigned long long* maxbits,
                   hipStream_t s, int tag, int variant) {
-  const int BK = variant == 1 ? 16 : 32;
+  const int BK = variant == 1 || variant == 3 ? 16 : 32;
   if (M < 1 || N < 2 || K < BK || K % BK != 0) return false;
   if ((lda & 1) || (ldb & 1)) return false;
   if (blayout == B_NCONTIG && (N & 1)) return false;
   if (((uintptr_t)A & 15) || ((uintptr_t)B & 15)) return false;
   if (blayout == B_KCONTIG && N < 1) return false;
-  if (variant == 1) {
+  if (variant == 3) {
+    if (tag == GEMM_TAG_C2)
+      launch_lds<4, 2, 16, GEMM_TAG_C2, 3>(A, lda, B, ldb, blayout, C, om, M, N, K, maxbits, s);
+    else if (tag == GEMM_TAG_ENV)
+      launch_lds<4, 2, 16, GEMM_TAG_ENV, 3>(A, lda, B, ldb, blayout, C, om, M, N, K, maxbits, s);
+    else
+      launch_lds<4, 2, 16, GEMM_TAG_OTHER, 3>(A, lda, B, ldb, blayout, C, om, M, N, K, maxbits, s);
+  } else if (variant == 1) {
     if (tag == GEMM_TAG_C2)
       launch_lds<4, 2, 16, GEMM_TAG_C2>(A, lda, B, ldb, blayout, C, om, M, N, K, maxbits, s);
     else if (tag == GEMM_TAG_ENV)

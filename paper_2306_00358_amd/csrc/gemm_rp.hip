@@ -83,7 +83,7 @@ __device__ __forceinline__ void rp_load(const void* __restrict__ hi, const void*
 
 // Block tile 256 x BN with 8 waves; each wave owns 16 TM rows x 64 columns
 // (TM MFMA tiles of 16 rows): TM = 4 for BN = 128, TM = 8 for BN = 256.
-template <int MODE, int OUT, int TAG, int TM, int BN>
+template <int MODE, int OUT, int TAG, int TM, int BN, int NST>
 __global__ __launch_bounds__(512) void k_gemm_rp(const void* __restrict__ Ahi,
                                                  const void* __restrict__ Alo, long long lda,
                                                  const void* __restrict__ Bhi,
@@ -118,18 +118,25 @@ __global__ __launch_bounds__(512) void k_gemm_rp(const void* __restrict__ Ahi,
   const int c0 = MODE == RP_F32 ? 2 * lg : lg;
   const int c1 = MODE == RP_F32 ? 2 * lg + 1 : 4 + lg;
 
+  static_assert(NST == 2 || NST == 3, "two or three LDS stages");
   const int nslab = K / 32;
   issue(0, 0);
+  if (NST == 3 && nslab > 1) issue(32, 1);
   for (int s = 0; s < nslab; ++s) {
-    const int cur = s & 1;
-    if (s + 1 < nslab) {
+    const int cur = NST == 2 ? (s & 1) : s % 3;
+    if (NST == 2 && s + 1 < nslab) {
       issue((s + 1) * 32, cur ^ 1);
       asm volatile("s_waitcnt vmcnt(%0)" ::"n"(LOADS) : "memory");
+    } else if (NST == 3 && s + 1 < nslab) {
+      asm volatile("s_waitcnt vmcnt(%0)" ::"n"(LOADS) : "memory");  // slab s+1 may be pending
     } else {
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     }
+    // slab s has landed for every wave; with three stages every wave has also
+    // finished reading slab s-1, whose stage takes slab s+2
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");
+    if (NST == 3 && s + 2 < nslab) issue((s + 2) * 32, (s + 2) % 3);
     const char* as = smem + cur * STAGE;
     const char* bs = as + A_BYTES;
     f4 a0[TM], a1[TM], b0[4], b1[4];
@@ -172,8 +179,10 @@ __global__ __launch_bounds__(512) void k_gemm_rp(const void* __restrict__ Ahi,
       }
     }
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-    __builtin_amdgcn_s_barrier();
-    asm volatile("" ::: "memory");
+    if (NST == 2) {
+      __builtin_amdgcn_s_barrier();
+      asm volatile("" ::: "memory");
+    }
   }
 
   float mx = 0.f;
@@ -217,21 +226,23 @@ __global__ __launch_bounds__(512) void k_gemm_rp(const void* __restrict__ Ahi,
   }
 }
 
-// block width: 256 columns (wave tile 128 x 64) when N allows, else 128
-static int rp_block_n(int N) {
+// tile configuration: 0 = 256 x 256 blocks, two stages (N >= 256);
+// 1 = 256 x 128 blocks, two stages; 2 = 256 x 128 blocks, three stages
+static int rp_config(int N) {
   static const int forced = [] {
-    const char* e = getenv("HOTRG_RP_BN");
-    return e ? atoi(e) : 0;
+    const char* e = getenv("HOTRG_RP_CFG");
+    return e ? atoi(e) : -1;
   }();
-  if (forced == 128 || forced == 256) return forced;
-  return N >= 256 ? 256 : 128;
+  if (forced == 0 && N >= 256) return 0;
+  if (forced == 1 || forced == 2) return forced;
+  return N >= 256 ? 0 : 1;
 }
 
-template <int MODE, int OUT, int TM, int BN>
+template <int MODE, int OUT, int TM, int BN, int NST>
 static void launch_rp_shape(int tag, const RpOperand& A, long long lda, const RpOperand& B,
                             long long ldb, void* C, void* Clo, const OutMap& om, int M, int N,
                             int K, unsigned long long* maxbits, hipStream_t s) {
-  constexpr int LDS = 2 * (256 + BN) * 128;
+  constexpr int LDS = NST * (256 + BN) * 128;
   dim3 grid((N + BN - 1) / BN, (M + 255) / 256);
   auto go = [&](auto kern) {
     static const bool ok = hipFuncSetAttribute((const void*)kern,
@@ -242,21 +253,24 @@ static void launch_rp_shape(int tag, const RpOperand& A, long long lda, const Rp
                        om, M, N, K, maxbits);
   };
   if (tag == GEMM_TAG_C2)
-    go(k_gemm_rp<MODE, OUT, GEMM_TAG_C2, TM, BN>);
+    go(k_gemm_rp<MODE, OUT, GEMM_TAG_C2, TM, BN, NST>);
   else if (tag == GEMM_TAG_ENV)
-    go(k_gemm_rp<MODE, OUT, GEMM_TAG_ENV, TM, BN>);
+    go(k_gemm_rp<MODE, OUT, GEMM_TAG_ENV, TM, BN, NST>);
   else
-    go(k_gemm_rp<MODE, OUT, GEMM_TAG_OTHER, TM, BN>);
+    go(k_gemm_rp<MODE, OUT, GEMM_TAG_OTHER, TM, BN, NST>);
 }
 
 template <int MODE, int OUT>
 static void launch_rp_tag(int tag, const RpOperand& A, long long lda, const RpOperand& B,
                           long long ldb, void* C, void* Clo, const OutMap& om, int M, int N,
                           int K, unsigned long long* maxbits, hipStream_t s) {
-  if (rp_block_n(N) == 256)
-    launch_rp_shape<MODE, OUT, 8, 256>(tag, A, lda, B, ldb, C, Clo, om, M, N, K, maxbits, s);
+  const int cfg = rp_config(N);
+  if (cfg == 0)
+    launch_rp_shape<MODE, OUT, 8, 256, 2>(tag, A, lda, B, ldb, C, Clo, om, M, N, K, maxbits, s);
+  else if (cfg == 2)
+    launch_rp_shape<MODE, OUT, 4, 128, 3>(tag, A, lda, B, ldb, C, Clo, om, M, N, K, maxbits, s);
   else
-    launch_rp_shape<MODE, OUT, 4, 128>(tag, A, lda, B, ldb, C, Clo, om, M, N, K, maxbits, s);
+    launch_rp_shape<MODE, OUT, 4, 128, 2>(tag, A, lda, B, ldb, C, Clo, om, M, N, K, maxbits, s);
 }
 
 bool gemm_rp(int mode, const RpOperand& A, long long lda, const RpOperand& B, long long ldb,
