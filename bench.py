@@ -281,6 +281,27 @@ def serve_errors(ctx, reqs, vals):
             for k, v in sorted(out.items())}
 
 
+def small_case(ctx, reps=20):
+    """The small configuration (Ising at T_c, D_cut = 8, 20 directional steps,
+    FP64): launch- and latency-bound; steps/s over `reps` runs."""
+    import torch
+
+    from paper_2306_00358_amd import hotrg_run, make_opts, model_params
+
+    params = model_params("ising", beta=BETA_C)
+    opts = make_opts(8, 20)
+    hotrg_run(ctx, params, opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        r = hotrg_run(ctx, params, opts)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    return {"workload": "Ising T_c, D_cut=8, 20 directional steps, fp64", "steps_per_s": 20 / dt,
+            "ms_per_run": dt * 1e3,
+            "rel_err_vs_onsager": abs(r["lnz_per_site"] - ONSAGER_TC) / ONSAGER_TC}
+
+
 def cpu_baseline(d_cut):
     """The oracle on the host cores: one steady-state directional step at
     dims (d_cut, d_cut, d_cut) of the same Ising run (the warm-up steps that
@@ -372,10 +393,15 @@ def main():
         c2_ms = sum(c2) / len(c2) if c2 else float("nan")
         achieved = step_flops(*steady)["c2"] / (c2_ms * 1e-3) / 1e12
         lnz = results[-1]["lnz_per_site"]
+        tflops = flops_run * args.steps / elapsed / 1e12
+        issued = 3.0 if prec == "bf16x3" else 1.0  # bf16 products per multiply-add
         return {
             "steps_per_s": args.n_steps * args.steps / elapsed,
             "ms_per_run": elapsed / args.steps * 1e3,
-            "tflops": flops_run * args.steps / elapsed / 1e12,
+            "tflops": tflops,
+            # whole run: issued MFMA flops over run time x peak (eigensolver included)
+            "run_frac_of_peak": issued * tflops / PEAKS[prec],
+            "eigh_share": phase_ms.get("eigh", 0.0) / (elapsed / args.steps * 1e3),
             "lnz_per_site": lnz,
             "rel_err_vs_fp64_oracle": abs(lnz - ref) / abs(ref) if ref is not None else None,
             "rel_err_vs_onsager": abs(lnz - ONSAGER_TC) / ONSAGER_TC,
@@ -413,6 +439,9 @@ def main():
                      "kernel": "C2 GEMM %dx%dx%d" % (args.d_cut**3, args.d_cut**2, args.d_cut**2),
                      "kernel_ms": head["c2_ms"], "launches": head["c2_launches"]},
     }
+    out["run_frac_of_peak"] = head["run_frac_of_peak"]
+    out["eigh_share"] = head["eigh_share"]
+    out["small_case"] = small_case(ctx)
     if not args.no_compare:
         # the same workload with reduced-precision contractions (eigensolver
         # and log-norm stay FP64)

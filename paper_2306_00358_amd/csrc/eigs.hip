@@ -12,8 +12,9 @@
 //             V = orth(Y) by shifted Cholesky-QR three times (Fukaya et al.,
 //             "Shifted Cholesky QR for computing the QR factorization of
 //             ill-conditioned matrices", SIAM J. Sci. Comput. 42 (2020)):
-//             G = Y Y^T + s I, G = R^T R, V = R^-T Y; the first pass uses
-//             s = 11 (n p + p(p+1)) u trace(G), the next two s = 0.
+//             G = Y Y^T + s I, G = R^T R, V = R^-T Y; the first pass factors
+//             the diagonally scaled G with s = 11 (n p + p(p+1)) u trace,
+//             the next two s = 0 (skipped between checks when G = I to 1e-8).
 // Check:      H = V (V M)^T, H = Z diag(theta) Z^T (rocSOLVER on p x p),
 //             Ritz vectors X = Z^T V, residuals |(Z^T Y)_i - theta_i X_i|.
 // Converged when the residuals of the `need` leading pairs are below
@@ -70,17 +71,19 @@ __global__ void k_seed_block(double* V, long long count, unsigned long long seed
 constexpr int kCholThreads = 256;
 
 __global__ __launch_bounds__(kCholThreads) void k_chol_inv(const double* __restrict__ G, int p,
-                                                           double shift_rel,
+                                                           double shift_rel, int scale,
+                                                           double identity_tol,
                                                            double* __restrict__ RinvT,
                                                            int* fail) {
   extern __shared__ double lds[];
   double* R = lds;             // p * p: R (upper, zeros below), later X^T
   double* P = R + p * p;       // 2 x 8 x 128 published rows
   __shared__ int bad;
+  __shared__ double dev[kCholThreads];
+  __shared__ double dsc[128];  // diag(G)^-1/2 when scaling, else 1
   const int t = threadIdx.x;
   const int tx = t & 15, ty = t >> 4;
   const int pm = p - 1;
-  for (int e = t; e < p * p; e += kCholThreads) R[e] = 0.0;
   double A[8][8];
 #pragma unroll
   for (int a = 0; a < 8; ++a)
@@ -89,7 +92,27 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_inv(const double* __restr
       const int i = min(ty + 16 * a, pm), k = min(tx + 16 * b, pm);
       A[a][b] = G[min(i, k) * p + max(i, k)];  // upper part, mirrored
     }
-  // trace: the diagonal owners publish, every thread sums in the same order
+  if (identity_tol > 0.0) {
+    // G already the identity to within identity_tol: R^-1 = I
+    double d = 0.0;
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const int i = ty + 16 * a, k = tx + 16 * b;
+        if (i < p && k < p) d = fmax(d, fabs(A[a][b] - (i == k ? 1.0 : 0.0)));
+      }
+    dev[t] = d;
+    __syncthreads();
+    double mx = 0.0;
+    for (int i = 0; i < kCholThreads; ++i) mx = fmax(mx, dev[i]);
+    if (mx <= identity_tol) {  // uniform: every thread reduced the same values
+      for (int e = t; e < p * p; e += kCholThreads) RinvT[e] = (e / p == e % p) ? 1.0 : 0.0;
+      return;
+    }
+  }
+  for (int e = t; e < p * p; e += kCholThreads) R[e] = 0.0;
+  // diagonal: the owners publish it
   if (tx == ty) {
 #pragma unroll
     for (int a = 0; a < 8; ++a)
@@ -97,8 +120,25 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_inv(const double* __restr
   }
   if (t == 0) bad = 0;
   __syncthreads();
+  // with `scale`, factor D^-1 G D^-1 (D = diag(G)^1/2) instead of G: the
+  // columns' lengths drop out of the conditioning, and the scaling is put
+  // back into the rows of R^-1 at the end
+  if (t < 128) dsc[t] = (scale && t < p) ? 1.0 / sqrt(P[t]) : 1.0;
+  __syncthreads();
+  if (scale) {
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      const double dr = dsc[min(ty + 16 * a, pm)];
+#pragma unroll
+      for (int b = 0; b < 8; ++b) A[a][b] *= dr * dsc[min(tx + 16 * b, pm)];
+    }
+  }
+  // trace (of the matrix factored), every thread sums in the same order
   double tr = 0.0;
-  for (int i = 0; i < p; ++i) tr += P[i];
+  if (scale)
+    tr = (double)p;
+  else
+    for (int i = 0; i < p; ++i) tr += P[i];
   const double shift = shift_rel * tr;
   if (tx == ty) {
 #pragma unroll
@@ -270,7 +310,8 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_inv(const double* __restr
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
       const int i = ty + 16 * a, k = tx + 16 * b;
-      if (i < p && k < p) R[k * p + i] = A[a][b];
+      // with scaling R = R^ D, so row i of R^-1 = D^-1 R^^-1 carries G_ii^-1/2
+      if (i < p && k < p) R[k * p + i] = A[a][b] * dsc[i];
     }
   __syncthreads();
   for (int e = t; e < p * p; e += kCholThreads) RinvT[e] = R[e];
@@ -381,13 +422,18 @@ bool topk_eigs(rocblas_handle blas, const double* M, int n, int p, int need, dou
   (void)hipMemsetAsync(fail, 0, sizeof(int), s);
   hipLaunchKernelGGL(k_seed_block, dim3(256), dim3(256), 0, s, V, (long long)pn, 12345ULL);
 
-  // one orthonormalisation of rows of Y into V
-  auto orth = [&](const double* Yin, double* Vout) {
+  // one orthonormalisation of rows of Y into V: shifted Cholesky-QR of the
+  // column-scaled Gram matrix, then two plain passes.  Between
+  // Rayleigh-Ritz checks the basis only has to stay well conditioned: there
+  // a pass whose Gram matrix is already the identity to 1e-8 is skipped
+  // (R^-1 = I); before a check every pass is done.
+  auto orth = [&](const double* Yin, double* Vout, bool full) {
     const double* src = Yin;
     for (int pass = 0; pass < 3; ++pass) {
       gemm_f64_splitk(src, n, src, n, B_KCONTIG, G, p, p, p, n, kc, part, s);
       hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(kCholThreads), lds, s, G, p,
-                         pass == 0 ? shift_rel : 0.0, Rt, fail);
+                         pass == 0 ? shift_rel : 0.0, pass == 0 ? 1 : 0,
+                         (pass == 0 || full) ? 0.0 : 1e-8, Rt, fail);
       double* dst = (pass == 2) ? Vout : (src == T2 ? Y : T2);
       if (dst == src) dst = (src == Y) ? T2 : Y;
       gemm_f64(Rt, p, src, n, B_NCONTIG, dst, out_rowmajor(n), p, n, p, nullptr, s);
@@ -407,7 +453,7 @@ bool topk_eigs(rocblas_handle blas, const double* M, int n, int p, int need, dou
   while (true) {
     for (int r = 0; r < q; ++r) {
       vm(V, Y);
-      orth(Y, V);
+      orth(Y, V, r == q - 1);
       ++it;
     }
     // Rayleigh-Ritz
