@@ -203,12 +203,18 @@ hotrg_status hotrg_submit(hotrg_ctx* ctx, const hotrg_model_params* params, cons
                           hotrg_result* result, uint64_t* ticket);
 /* HOTRG_ERR_NOT_READY while queued or running; afterwards the problem's own
  * status (HOTRG_OK, an error, or HOTRG_ERR_CANCELLED).  A finished ticket
- * stays valid until the context is destroyed. */
+ * stays valid until hotrg_release or the context's destruction. */
 hotrg_status hotrg_poll(hotrg_ctx* ctx, uint64_t ticket);
 /* Wait up to timeout_s seconds (< 0: no limit); returns as hotrg_poll. */
 hotrg_status hotrg_wait(hotrg_ctx* ctx, uint64_t ticket, double timeout_s);
 /* Cancel a queued problem, or stop a running one at its next step boundary. */
 hotrg_status hotrg_cancel(hotrg_ctx* ctx, uint64_t ticket);
+/* Forget a finished ticket: its record (and the copy of a HOTRG_RAW tensor)
+ * is freed and later calls with it return HOTRG_ERR_INVALID.
+ * HOTRG_ERR_NOT_READY while the problem is queued or running.  A serving
+ * loop releases every ticket it has read, so the context's bookkeeping stays
+ * bounded; hotrg_run_batch releases its own. */
+hotrg_status hotrg_release(hotrg_ctx* ctx, uint64_t ticket);
 /* Estimated peak device bytes of one problem (the admission footprint). */
 hotrg_status hotrg_footprint(const hotrg_model_params* params, const hotrg_opts* opts,
                              size_t* bytes);

@@ -30,6 +30,7 @@ EXPORTS = [
     "hotrg_run", "hotrg_environment", "hotrg_coarse", "hotrg_ctx_enable_timing", "hotrg_ctx_timings",
     "hotrg_ctx_set_workers", "hotrg_submit", "hotrg_poll", "hotrg_wait", "hotrg_cancel",
     "hotrg_footprint", "hotrg_run_batch", "hotrg_ctx_sched_stats", "hotrg_thermo",
+    "hotrg_release",
 ]
 
 PHASES = ["env", "eigh", "proj", "c1", "c2", "c3", "norm"]
@@ -108,6 +109,7 @@ def lib():
     L.hotrg_poll.argtypes = [vp, ctypes.c_uint64]
     L.hotrg_wait.argtypes = [vp, ctypes.c_uint64, c_double]
     L.hotrg_cancel.argtypes = [vp, ctypes.c_uint64]
+    L.hotrg_release.argtypes = [vp, ctypes.c_uint64]
     L.hotrg_footprint.argtypes = [POINTER(ModelParams), POINTER(Opts), POINTER(c_size_t)]
     L.hotrg_run_batch.argtypes = [vp, c_int, POINTER(ModelParams), POINTER(Opts), POINTER(Result),
                                   POINTER(c_int)]
@@ -359,10 +361,18 @@ class Ticket:
     def cancel(self):
         _check(lib().hotrg_cancel(self.ctx.ptr, self.id))
 
+    def release(self):
+        """Forget the finished ticket (hotrg_release)."""
+        _check(lib().hotrg_release(self.ctx.ptr, self.id))
+
     def value(self):
+        """Wait, release the ticket and return the result (raises on failure)."""
         st = self.wait()
+        err = lib().hotrg_last_error().decode() if st != HOTRG_OK else ""
+        if st != HOTRG_ERR_NOT_READY:
+            self.release()
         if st != HOTRG_OK:
-            raise HotrgError(st, lib().hotrg_last_error().decode())
+            raise HotrgError(st, err)
         return _result_dict(self.result, self.infos, self.spec, self.opts.n_steps, self.opts.spec_len)
 
 

@@ -461,6 +461,26 @@ hotrg_status hotrg_cancel(hotrg_ctx* ctx, uint64_t ticket) {
   return HOTRG_OK;
 }
 
+hotrg_status hotrg_release(hotrg_ctx* ctx, uint64_t ticket) {
+  Server* S = ctx ? server_of(ctx, false) : nullptr;
+  if (!S) {
+    set_last_error("no such ticket");
+    return HOTRG_ERR_INVALID;
+  }
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->all.find(ticket);
+  if (it == S->all.end()) {
+    set_last_error("no such ticket");
+    return HOTRG_ERR_INVALID;
+  }
+  if (it->second->state != Q_DONE) {
+    set_last_error("problem still queued or running");
+    return HOTRG_ERR_NOT_READY;
+  }
+  S->all.erase(it);
+  return HOTRG_OK;
+}
+
 hotrg_status hotrg_run_batch(hotrg_ctx* ctx, int n, const hotrg_model_params* params,
                              const hotrg_opts* opts, hotrg_result* results,
                              hotrg_status* statuses) {
@@ -484,7 +504,10 @@ hotrg_status hotrg_run_batch(hotrg_ctx* ctx, int n, const hotrg_model_params* pa
   hotrg_status first = HOTRG_OK;
   std::string first_err;
   for (int i = 0; i < n; ++i) {
-    if (st[i] == HOTRG_OK) st[i] = hotrg_wait(ctx, tickets[i], -1.0);
+    if (st[i] == HOTRG_OK) {
+      st[i] = hotrg_wait(ctx, tickets[i], -1.0);
+      (void)hotrg_release(ctx, tickets[i]);
+    }
     if (statuses) statuses[i] = st[i];
     if (st[i] != HOTRG_OK && first == HOTRG_OK) {
       first = st[i];

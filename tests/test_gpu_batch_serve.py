@@ -222,3 +222,17 @@ def test_numeric_failure_reruns_in_fp64(torch_cuda):
     else:
         assert got["prec_used"] == HOTRG_BF16X3
         assert abs(got["lnz_per_site"] - want) <= 1e-4 * abs(want)
+
+
+def test_released_ticket_is_forgotten(torch_cuda):
+    from paper_2306_00358_amd import Context, Ticket, make_opts, model_params
+    from paper_2306_00358_amd._lib import HOTRG_ERR_INVALID, HOTRG_OK
+
+    with Context(0) as ctx:
+        t = Ticket(ctx, model_params("ising", beta=0.44), make_opts(8, 10))
+        assert t.wait() == HOTRG_OK
+        assert t.poll() == HOTRG_OK  # still known after wait
+        t.release()
+        assert t.poll() == HOTRG_ERR_INVALID
+        v = Ticket(ctx, model_params("ising", beta=0.44), make_opts(8, 10)).value()
+        assert math.isfinite(v["lnz_per_site"])
