@@ -112,3 +112,37 @@ def test_struct_offsets_match_the_c_compiler(tmp_path):
         assert got[(cname, "sizeof")] == ctypes.sizeof(py), cname
         for f, _ in py._fields_:
             assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
+def test_c_program_compiles_and_links(tmp_path):
+    # a plain C99 caller of the boundary builds and links against libhotrg.so
+    # (it is not run here: running needs a GPU)
+    import shutil
+    import subprocess
+
+    from paper_2306_00358_amd import _lib
+
+    if not shutil.which("gcc"):
+        pytest.skip("gcc not available")
+    src = tmp_path / "caller.c"
+    src.write_text("""
+#include <stdio.h>
+#include "hotrg.h"
+int main(void) {
+  hotrg_ctx* ctx;
+  if (hotrg_ctx_create(0, NULL, 0, &ctx) != HOTRG_OK) { puts(hotrg_last_error()); return 1; }
+  hotrg_model_params p = {0};
+  p.model = HOTRG_ISING; p.beta = 0.4406867935097715; p.J = 1.0;
+  hotrg_opts o = {0};
+  o.d_cut = 16; o.n_steps = 20; o.prec = HOTRG_FP64;
+  hotrg_result r = {0};
+  if (hotrg_run(ctx, &p, &o, &r) != HOTRG_OK) { puts(hotrg_last_error()); return 1; }
+  printf("%.15f\\n", r.lnz_per_site);
+  hotrg_ctx_destroy(ctx);
+  return 0;
+}
+""")
+    libdir = os.path.dirname(_lib.LIB_PATH)
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                    str(tmp_path / "caller"), "-L", libdir, "-lhotrg", "-Wl,-rpath," + libdir],
+                   check=True)
