@@ -13,6 +13,9 @@
 
 #include <cstdlib>
 
+#include <map>
+#include <mutex>
+
 #include "internal.h"
 
 namespace hotrg {
@@ -363,37 +366,162 @@ static void launch_big(const double* A, long long lda, const double* B, long lon
                        om, M, N, K, maxbits);
 }
 
+// ------------------------------------------------------------- autotuner --
+// Large products (M * N >= 2^20) pick their kernel by measurement: on the
+// first call with a given shape, operand strides, layout, output map and tag,
+// every applicable candidate runs twice on the caller's operands and stream,
+// timed with HIP events (the second run counts: the first loads code and
+// warms caches); the fastest is kept for the rest of the process and
+// produces the output of that first call too.  Candidates differ only in
+// tiling (same products, different summation order), so results agree to
+// rounding.  HOTRG_AUTOTUNE=0 keeps the fixed rule below; HOTRG_GEMM_VARIANT
+// forces one kernel.
+namespace {
+
+enum { C_LDS2 = 0, C_LDS3, C_LDS32, C_LDS_HALF, C_BIG, C_G128, C_G64, C_COUNT };
+
+struct TuneKey {
+  long long v[16];
+  bool operator<(const TuneKey& o) const {
+    for (int i = 0; i < 16; ++i)
+      if (v[i] != o.v[i]) return v[i] < o.v[i];
+    return false;
+  }
+};
+
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tune;
+
+bool autotune_on() {
+  static const bool on = [] {
+    const char* e = std::getenv("HOTRG_AUTOTUNE");
+    return !(e && e[0] == '0');
+  }();
+  return on;
+}
+
+TuneKey make_key(int prec, long long lda, long long ldb, int bl, const OutMap& om, int M, int N,
+                 int K, bool mx, int tag) {
+  TuneKey k{};
+  const long long v[16] = {prec, lda, ldb, bl, M, N, K, mx, tag, om.r1, om.r2, om.s0,
+                           om.c1, om.c2, om.t0, om.s1 * 1000003LL + om.s2 + om.t1 * 7919LL + om.t2};
+  for (int i = 0; i < 16; ++i) k.v[i] = v[i];
+  return k;
+}
+
+// time each applicable candidate (second of two runs); -1 if none applies
+// The lock is held through a measurement, so each shape is measured once
+// per process and every call sees the same choice.
+template <class Run>
+int tune(const TuneKey& key, int count, Run&& run, hipStream_t s, bool* tuned) {
+  *tuned = false;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find(key);
+  if (it != g_tune.end()) return it->second;
+  *tuned = true;
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess) return -1;
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return -1;
+  }
+  int best = -1;
+  float best_ms = 0.f;
+  for (int c = 0; c < count; ++c) {
+    if (!run(c)) continue;  // not applicable to this shape
+    (void)hipEventRecord(a, s);
+    run(c);
+    (void)hipEventRecord(b, s);
+    float ms = 0.f;
+    if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess)
+      continue;
+    if (best < 0 || ms < best_ms) {
+      best = c;
+      best_ms = ms;
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (best >= 0) g_tune[key] = best;
+  return best;
+}
+
+}  // namespace
+
 void gemm_f64(const double* A, long long lda, const double* B, long long ldb, int blayout,
               double* C, const OutMap& om, int M, int N, int K, unsigned long long* maxbits,
               hipStream_t s, int tag) {
   if (M <= 0 || N <= 0) return;
-  // kernel choice for large products: HOTRG_GEMM_VARIANT (tuning only)
   static const int forced = [] {
     const char* e = std::getenv("HOTRG_GEMM_VARIANT");
     return e ? std::atoi(e) : -1;
   }();
-  // default: 256 x 128 tiles, three LDS stages for long K (one barrier per
+  auto cand = [&](int c) -> bool {
+    switch (c) {
+      case C_LDS2:
+        return N >= 128 && gemm_f64_lds(A, lda, B, ldb, blayout, C, om, M, N, K, maxbits, s, tag, 1);
+      case C_LDS3:
+        return N >= 128 && K >= 64 &&
+               gemm_f64_lds(A, lda, B, ldb, blayout, C, om, M, N, K, maxbits, s, tag, 3);
+      case C_LDS32:
+        return N >= 128 && gemm_f64_lds(A, lda, B, ldb, blayout, C, om, M, N, K, maxbits, s, tag, 0);
+      case C_LDS_HALF:
+        return N >= 128 && gemm_f64_lds(A, lda, B, ldb, blayout, C, om, M, N, K, maxbits, s, tag, 4);
+      case C_BIG:
+        if (N < 128 || K < 64) return false;
+        switch (tag) {
+          case GEMM_TAG_C2:
+            launch_big<GEMM_TAG_C2>(A, lda, B, ldb, blayout, C, om, M, N, K, maxbits, s);
+            break;
+          case GEMM_TAG_ENV:
+            launch_big<GEMM_TAG_ENV>(A, lda, B, ldb, blayout, C, om, M, N, K, maxbits, s);
+            break;
+          default:
+            launch_big<GEMM_TAG_OTHER>(A, lda, B, ldb, blayout, C, om, M, N, K, maxbits, s);
+        }
+        return true;
+      case C_G128:
+        if (N < 128) return false;
+        launch_f64<128, 128, 16>(A, lda, B, ldb, blayout, C, om, M, N, K, maxbits, s);
+        return true;
+      default:
+        launch_f64<64, 64, 16>(A, lda, B, ldb, blayout, C, om, M, N, K, maxbits, s);
+        return true;
+    }
+  };
+  if (forced < 0 && autotune_on() && (long long)M * N >= (1LL << 20)) {
+    bool tuned = false;
+    const int c = tune(make_key(0, lda, ldb, blayout, om, M, N, K, maxbits != nullptr, tag),
+                       C_COUNT, cand, s, &tuned);
+    // the candidates' runs all reached the output max: start it again
+    if (tuned && maxbits) (void)hipMemsetAsync(maxbits, 0, 8, s);
+    if (c >= 0 && cand(c)) return;
+  }
+  // fixed rule: 256 x 128 tiles, three LDS stages for long K (one barrier per
   // slab, two slabs in flight), two for short K
   const int variant = forced >= 0 ? forced : (K >= 256 ? 3 : 1);
   if ((long long)M * N >= (1LL << 20) && N >= 128 && variant != 2 &&
       gemm_f64_lds(A, lda, B, ldb, blayout, C, om, M, N, K, maxbits, s, tag, variant))
     return;
   if ((long long)M * N >= (1LL << 22) && N >= 128 && K >= 64) {
-    switch (tag) {
-      case GEMM_TAG_C2:
-        launch_big<GEMM_TAG_C2>(A, lda, B, ldb, blayout, C, om, M, N, K, maxbits, s);
-        break;
-      case GEMM_TAG_ENV:
-        launch_big<GEMM_TAG_ENV>(A, lda, B, ldb, blayout, C, om, M, N, K, maxbits, s);
-        break;
-      default:
-        launch_big<GEMM_TAG_OTHER>(A, lda, B, ldb, blayout, C, om, M, N, K, maxbits, s);
-    }
+    cand(C_BIG);
   } else if ((long long)M * N >= (1LL << 22) && N >= 128) {
     launch_f64<128, 128, 16>(A, lda, B, ldb, blayout, C, om, M, N, K, maxbits, s);
   } else {
     launch_f64<64, 64, 16>(A, lda, B, ldb, blayout, C, om, M, N, K, maxbits, s);
   }
+}
+
+// the autotuner's table, for the reduced-precision launcher
+int tune_choice(int prec, long long lda, long long ldb, int bl, const OutMap& om, int M, int N,
+                int K, unsigned long long* maxbits, int tag, int count,
+                bool (*run)(void*, int), void* ctx, hipStream_t s) {
+  if (!autotune_on()) return -1;
+  bool tuned = false;
+  const int c = tune(make_key(prec, lda, ldb, bl, om, M, N, K, maxbits != nullptr, tag), count,
+                     [&](int k) { return run(ctx, k); }, s, &tuned);
+  if (tuned && maxbits) (void)hipMemsetAsync(maxbits, 0, 8, s);
+  return c;
 }
 
 }  // namespace hotrg

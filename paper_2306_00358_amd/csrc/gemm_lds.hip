@@ -272,13 +272,21 @@ static void launch_lds(const double* A, long long lda, const double* B, long lon
 bool gemm_f64_lds(const double* A, long long lda, const double* B, long long ldb, int blayout,
                   double* C, const OutMap& om, int M, int N, int K, unsigned long long* maxbits,
                   hipStream_t s, int tag, int variant) {
-  const int BK = variant == 1 || variant == 3 ? 16 : 32;
+  const int BK = variant == 0 ? 32 : 16;
   if (M < 1 || N < 2 || K < BK || K % BK != 0) return false;
   if ((lda & 1) || (ldb & 1)) return false;
   if (blayout == B_NCONTIG && (N & 1)) return false;
   if (((uintptr_t)A & 15) || ((uintptr_t)B & 15)) return false;
   if (blayout == B_KCONTIG && N < 1) return false;
-  if (variant == 3) {
+  if (variant == 4) {
+    // 128 x 128 tile, 4 waves, 64 KB of LDS: two workgroups per CU
+    if (tag == GEMM_TAG_C2)
+      launch_lds<2, 2, 16, GEMM_TAG_C2>(A, lda, B, ldb, blayout, C, om, M, N, K, maxbits, s);
+    else if (tag == GEMM_TAG_ENV)
+      launch_lds<2, 2, 16, GEMM_TAG_ENV>(A, lda, B, ldb, blayout, C, om, M, N, K, maxbits, s);
+    else
+      launch_lds<2, 2, 16, GEMM_TAG_OTHER>(A, lda, B, ldb, blayout, C, om, M, N, K, maxbits, s);
+  } else if (variant == 3) {
     if (tag == GEMM_TAG_C2)
       launch_lds<4, 2, 16, GEMM_TAG_C2, 3>(A, lda, B, ldb, blayout, C, om, M, N, K, maxbits, s);
     else if (tag == GEMM_TAG_ENV)

@@ -261,16 +261,49 @@ static void launch_rp_shape(int tag, const RpOperand& A, long long lda, const Rp
 }
 
 template <int MODE, int OUT>
-static void launch_rp_tag(int tag, const RpOperand& A, long long lda, const RpOperand& B,
-                          long long ldb, void* C, void* Clo, const OutMap& om, int M, int N,
-                          int K, unsigned long long* maxbits, hipStream_t s) {
-  const int cfg = rp_config(N);
+static void launch_rp_cfg(int cfg, int tag, const RpOperand& A, long long lda,
+                          const RpOperand& B, long long ldb, void* C, void* Clo,
+                          const OutMap& om, int M, int N, int K, unsigned long long* maxbits,
+                          hipStream_t s) {
   if (cfg == 0)
     launch_rp_shape<MODE, OUT, 8, 256, 2>(tag, A, lda, B, ldb, C, Clo, om, M, N, K, maxbits, s);
   else if (cfg == 2)
     launch_rp_shape<MODE, OUT, 4, 128, 3>(tag, A, lda, B, ldb, C, Clo, om, M, N, K, maxbits, s);
   else
     launch_rp_shape<MODE, OUT, 4, 128, 2>(tag, A, lda, B, ldb, C, Clo, om, M, N, K, maxbits, s);
+}
+
+template <int MODE, int OUT>
+static void launch_rp_tag(int tag, const RpOperand& A, long long lda, const RpOperand& B,
+                          long long ldb, void* C, void* Clo, const OutMap& om, int M, int N,
+                          int K, unsigned long long* maxbits, hipStream_t s) {
+  static const bool forced = getenv("HOTRG_RP_CFG") != nullptr;
+  if (!forced && (long long)M * N >= (1LL << 20)) {
+    struct Args {
+      int tag;
+      const RpOperand *A, *B;
+      long long lda, ldb;
+      void *C, *Clo;
+      const OutMap* om;
+      int M, N, K;
+      unsigned long long* maxbits;
+      hipStream_t s;
+    } args{tag, &A, &B, lda, ldb, C, Clo, &om, M, N, K, maxbits, s};
+    auto run = [](void* p, int cfg) -> bool {
+      const Args& a = *(const Args*)p;
+      if (cfg == 0 && a.N < 256) return false;
+      launch_rp_cfg<MODE, OUT>(cfg, a.tag, *a.A, a.lda, *a.B, a.ldb, a.C, a.Clo, *a.om, a.M,
+                               a.N, a.K, a.maxbits, a.s);
+      return true;
+    };
+    const int cfg = tune_choice(10 * MODE + OUT + 1, lda, ldb, 0, om, M, N, K, maxbits, tag, 3,
+                                run, &args, s);
+    if (cfg >= 0) {
+      run(&args, cfg);
+      return;
+    }
+  }
+  launch_rp_cfg<MODE, OUT>(rp_config(N), tag, A, lda, B, ldb, C, Clo, om, M, N, K, maxbits, s);
 }
 
 bool gemm_rp(int mode, const RpOperand& A, long long lda, const RpOperand& B, long long ldb,

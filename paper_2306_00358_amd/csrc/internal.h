@@ -74,6 +74,13 @@ struct RpOperand {
 // C[map(m,n)] = sum_k A[m][k] B[n][k]; rows of lda / ldb elements (multiples
 // of 8, zero past the true K); K a multiple of 32.  Output as float, split
 // bf16 (C = hi, Clo = lo) or double.  Returns false if a requirement fails.
+// Autotuner table shared by the GEMM launchers: the fastest of `count`
+// candidates (run(ctx, c) launches candidate c, false if it does not apply)
+// for this shape, measured on first use; -1 if tuning is off.  If it had to
+// measure, *maxbits (when given) is zeroed again for the final run.
+int tune_choice(int prec, long long lda, long long ldb, int bl, const OutMap& om, int M, int N,
+                int K, unsigned long long* maxbits, int tag, int count,
+                bool (*run)(void*, int), void* ctx, hipStream_t s);
 bool gemm_rp(int mode, const RpOperand& A, long long lda, const RpOperand& B, long long ldb,
              int out, void* C, void* Clo, const OutMap& om, int M, int N, int K,
              unsigned long long* maxbits, hipStream_t s, int tag);
