@@ -11,7 +11,11 @@ size 2^-52 (one rounding error); the parity tolerance of step k is then
 max(floor, factor * drift_k).  The same perturbed run gives the drift of
 ln Z/N and the kept counts a perturbed but correct run may choose; the
 ln Z/N tolerance is max(floor, factor * lnz drift), and kept counts are
-compared only at steps where the perturbed run kept the same number.
+compared only at steps where the perturbed run kept the same number and
+every gap the multiplet rule looks at clears the threshold by more than the
+spectra tolerance allows the values to move (`cut_is_robust`): the rule is a
+step function of the spectrum, so at a gap within that distance of tau both
+cuts are correct results.
 """
 
 import numpy as np
@@ -64,3 +68,24 @@ def spectra_tolerances(drift):
 
 def lnz_tolerance(lnz_drift):
     return max(LNZ_FLOOR, LNZ_FACTOR * lnz_drift)
+
+
+def cut_is_robust(spectrum, n, d_new, tau, delta):
+    """Whether the multiplet-safe cut of a spectrum (lambda / lambda_1,
+    descending, at least d_new + 1 values when d_new < n) stays the same
+    when every value moves by at most ``delta``.  The rule lowers the kept
+    count from d_new while the gap below it is at most tau; each gap it
+    examines, the last one included, must differ from tau by more than
+    2 * delta (a gap is the difference of two moved values)."""
+    if d_new >= n:
+        return True  # nothing is truncated
+    s = np.asarray(spectrum, dtype=np.float64)
+    kept = d_new
+    while kept > 0:
+        gap = s[kept - 1] - s[kept]
+        if abs(gap - tau) <= 2.0 * delta:
+            return False
+        if gap > tau:
+            return True
+        kept -= 1
+    return True

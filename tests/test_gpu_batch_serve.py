@@ -114,7 +114,7 @@ def test_xy_batch_vs_stored_oracle(torch_cuda):
     with Context(0) as ctx:
         got, st = hotrg_run_batch(ctx, params, opts, with_steps=True)
     assert st == [0] * len(runs)
-    from tests.sensitivity import lnz_tolerance, spectra_tolerances
+    from tests.sensitivity import cut_is_robust, lnz_tolerance, spectra_tolerances
 
     for r, g in zip(runs, got):
         # XY spectra hold exact multiplets, and at some couplings a gap at
@@ -125,7 +125,10 @@ def test_xy_batch_vs_stored_oracle(torch_cuda):
         say("xy", r["index"], "rel", rel, "drift", r["lnz_drift"])
         assert rel <= lnz_tolerance(r["lnz_drift"]), (r["index"], rel)
         tol = spectra_tolerances(r["spectra_drift"])
-        stable = [a["kept"] == b for a, b in zip(r["steps"], r["kept_perturbed"])]
+        # a cut is compared where the perturbed oracle made it too and no gap
+        # the multiplet rule examines lies within the tolerance of tau
+        stable = [a["kept"] == b and cut_is_robust(ws, a["dx"] * a["dx"], a["d_new"], r["tau"], t)
+                  for a, b, ws, t in zip(r["steps"], r["kept_perturbed"], r["spectra"], tol)]
         for k, (gs, ws) in enumerate(zip(g["spectra"], r["spectra"])):
             if not all(stable[:k]):
                 break  # an earlier cut is not fixed by the oracle either
