@@ -9,19 +9,29 @@
 // the rate lambda_{p+1} / lambda_{D'} per sweep.
 //
 // One sweep:  Y = V M  (rows of V are the p basis vectors)
-//             V = orth(Y) by shifted Cholesky-QR three times (Fukaya et al.,
-//             "Shifted Cholesky QR for computing the QR factorization of
+//             V = orth(Y) by shifted Cholesky-QR (Fukaya et al., "Shifted
+//             Cholesky QR for computing the QR factorization of
 //             ill-conditioned matrices", SIAM J. Sci. Comput. 42 (2020)):
 //             G = Y Y^T + s I, G = R^T R, V = R^-T Y; the first pass factors
 //             the diagonally scaled G with s = 11 (n p + p(p+1)) u trace,
-//             the next two s = 0 (skipped between checks when G = I to 1e-8).
+//             the next ones s = 0.  Before a check three passes make V
+//             orthonormal to rounding.  Between checks V only has to stay a
+//             well-conditioned basis of the same span: one pass after the
+//             first, which the device leaves out (R^-1 = I) when G is
+//             already the identity to 1e-2 -- after the first pass it is
+//             typically so to 1e-7..1e-4, except in a solve's first sweep.
 // Check:      H = V (V M)^T, H = Z diag(theta) Z^T (rocSOLVER on p x p),
 //             Ritz vectors X = Z^T V, residuals |(Z^T Y)_i - theta_i X_i|.
 // Converged when the residuals of the `need` leading pairs are below
 // tol * theta_1; otherwise the sweeps continue from X.  The first check
-// comes after q_first sweeps (the caller passes the count the previous
-// solve of the same kind needed, so most solves take one Rayleigh-Ritz).  All products are
-// FP64 MFMA GEMMs; the host reads p Ritz values and residuals per check.
+// comes after q_first sweeps.  On convergence `enough` estimates the fewest
+// sweeps that would have met the tolerance: the residual of the slowest
+// needed pair shrinks by about theta_min / theta_need per sweep, so a result
+// k such factors below tol was k sweeps more than necessary.  The caller
+// starts the next solve of the same kind from that estimate plus one, so most
+// solves take a single Rayleigh-Ritz without sweeping far past convergence.
+// All products are FP64 MFMA GEMMs; the host reads p Ritz values and
+// residuals per check.
 #include <hip/hip_runtime.h>
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
@@ -394,7 +404,7 @@ size_t topk_workspace_doubles(int n, int p) {
 // vectors (rows, same order) in Xout (p x n) on convergence.
 bool topk_eigs(rocblas_handle blas, const double* M, int n, int p, int need, double tol,
                int q_first, double* ws, double* W, double* Xout, int* dinfo, int* iters,
-               double* resid, hipStream_t s) {
+               int* enough, double* resid, hipStream_t s) {
   const size_t pn = (size_t)p * n, pp = (size_t)p * p;
   const int kc = splitk_chunk(n);
   const int kv = vm_chunk(n);
@@ -423,18 +433,18 @@ bool topk_eigs(rocblas_handle blas, const double* M, int n, int p, int need, dou
   hipLaunchKernelGGL(k_seed_block, dim3(256), dim3(256), 0, s, V, (long long)pn, 12345ULL);
 
   // one orthonormalisation of rows of Y into V: shifted Cholesky-QR of the
-  // column-scaled Gram matrix, then two plain passes.  Between
-  // Rayleigh-Ritz checks the basis only has to stay well conditioned: there
-  // a pass whose Gram matrix is already the identity to 1e-8 is skipped
-  // (R^-1 = I); before a check every pass is done.
+  // column-scaled Gram matrix, then plain passes -- two before a
+  // Rayleigh-Ritz check (`full`), else one that is skipped on the device
+  // (R^-1 = I) when its Gram matrix is the identity to 1e-2.
   auto orth = [&](const double* Yin, double* Vout, bool full) {
     const double* src = Yin;
-    for (int pass = 0; pass < 3; ++pass) {
+    const int last = full ? 2 : 1;
+    for (int pass = 0; pass <= last; ++pass) {
       gemm_f64_splitk(src, n, src, n, B_KCONTIG, G, p, p, p, n, kc, part, s);
       hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(kCholThreads), lds, s, G, p,
                          pass == 0 ? shift_rel : 0.0, pass == 0 ? 1 : 0,
-                         (pass == 0 || full) ? 0.0 : 1e-8, Rt, fail);
-      double* dst = (pass == 2) ? Vout : (src == T2 ? Y : T2);
+                         (pass == 0 || full) ? 0.0 : 1e-2, Rt, fail);
+      double* dst = (pass == last) ? Vout : (src == T2 ? Y : T2);
       if (dst == src) dst = (src == Y) ? T2 : Y;
       gemm_f64(Rt, p, src, n, B_NCONTIG, dst, out_rowmajor(n), p, n, p, nullptr, s);
       src = dst;
@@ -478,13 +488,19 @@ bool topk_eigs(rocblas_handle blas, const double* M, int n, int p, int need, dou
     if (!(t1 > 0.0)) return false;
     double top = 0.0;
     for (int i = 0; i < need; ++i) top = std::fmax(top, rs[p - 1 - i] / t1);
-    if (iters) *iters = it;
-    if (resid) *resid = top;
-    if (top <= tol) return true;
-    if (it >= max_it || !(top < 0.5 * prev)) return false;
-    prev = top;
     double rate = th[p - need] > 0.0 ? th[0] / th[p - need] : 0.5;
     rate = std::fmin(std::fmax(rate, 1e-6), 0.95);
+    if (iters) *iters = it;
+    if (resid) *resid = top;
+    if (top <= tol) {
+      // sweeps beyond the first that met tol: top / rate^k <= tol
+      int extra = top > 0.0 ? (int)std::floor(std::log(top / tol) / std::log(rate)) : it;
+      extra = extra < 0 ? 0 : extra;
+      if (enough) *enough = it - extra < 1 ? 1 : it - extra;
+      return true;
+    }
+    if (it >= max_it || !(top < 0.5 * prev)) return false;
+    prev = top;
     q = (int)std::ceil(std::log(tol / top) / std::log(rate));
     q = q < 1 ? 1 : (q > max_it - it ? max_it - it : q);
     // continue from the Ritz vectors

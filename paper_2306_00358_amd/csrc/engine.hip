@@ -524,17 +524,17 @@ void do_step(hotrg_ctx* c, hotrg_state* st, const hotrg_opts* o) {
     if (sub) {
       ensure(c, c->EW, topk_workspace_doubles(n, p) * 8);
       ensure(c, Xb, (size_t)p * n * 8);
-      int iters = 0;
+      int iters = 0, enough = 0;
       double resid = 0.0;
       // steps of equal parity see environments of the same kind: start with
-      // one sweep more than the last such solve needed
+      // one sweep more than the last such solve is estimated to have needed
       const int slot = (st->k & 1) + 2 * side;
       const int q_first = st->eig_n[slot] == n ? st->eig_sweeps[slot] + 1 : 3;
       sub = topk_eigs(c->blas, (const double*)Mb.p, n, p, need, 5e-14, q_first,
                       (double*)c->EW.p, (double*)Wb.p, (double*)Xb.p,
-                      (int*)((char*)c->scal.p + 48), &iters, &resid, c->stream);
+                      (int*)((char*)c->scal.p + 48), &iters, &enough, &resid, c->stream);
       st->eig_n[slot] = sub ? n : 0;
-      st->eig_sweeps[slot] = iters;
+      st->eig_sweeps[slot] = enough;
       c->last_eig_iters = sub ? iters : 0;
       c->last_eig_resid = resid;
       if (sub) {

@@ -130,7 +130,7 @@ void launch_trace(const double* M, int n, double* out, hipStream_t s);
 size_t topk_workspace_doubles(int n, int p);
 bool topk_eigs(rocblas_handle blas, const double* M, int n, int p, int need, double tol,
                int q_first, double* ws, double* W, double* Xout, int* dinfo, int* iters,
-               double* resid, hipStream_t s);
+               int* enough, double* resid, hipStream_t s);
 void launch_layout_u(const double* Ucan, int dx, int dn, void* U1, void* U3, bool out_f32,
                      hipStream_t s);
 void launch_norm(const unsigned long long* maxbits, const void* Tt, bool f32, int dn, int dy,
