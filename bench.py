@@ -18,6 +18,13 @@ result's ln Z/N error against the stored FP64 oracle.  The dominant kernel
 is the D^7 contraction (C2); its average duration over the steady-state
 steps of the timed runs comes from HIP events recorded on the library's
 stream around each phase.
+
+    python bench.py --batch             # 64 XY problems on the worker pool
+    python bench.py --serve N [--serve-loads 0.8,0.5,1.0,1.2]
+
+`--serve` replays a seeded stream of N mixed requests at Poisson arrival
+rates given as fractions of the saturation rate measured closed-loop on a
+prefix; the first load is the result, the others go to `load_sweep`.
 """
 
 import argparse
@@ -61,6 +68,10 @@ def parse():
                     help="skip the FP64 re-run of the served requests")
     ap.add_argument("--serve-check-max", type=int, default=40,
                     help="FP64 re-run of the first N served requests (bounded time)")
+    ap.add_argument("--serve-loads", default="0.8",
+                    help="comma-separated arrival rates as fractions of the measured "
+                         "saturation rate; the stream at the first one is the result, "
+                         "the others are reported under load_sweep")
     ap.add_argument("--workers", type=int, default=8)
     ap.add_argument("--kernel-probe", action="store_true",
                     help="run one coarse contraction at the benchmark shape and a 1 GiB "
@@ -187,14 +198,55 @@ def serve_requests(n, seed=0):
     return reqs
 
 
-def run_serve_bench(args):
+def serve_stream(ctx, reqs, rate, seed, tag):
+    """Submit the requests at Poisson arrival times of the given rate (seeded)
+    and wait for all of them.  Returns (results, wall seconds)."""
     import numpy as np
     import torch
 
+    from paper_2306_00358_amd import Ticket
+
+    arrivals = np.cumsum(np.random.default_rng(seed).exponential(1.0 / rate, size=len(reqs)))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tickets = []
+    for (p, o), ta in zip(reqs, arrivals):
+        while time.perf_counter() - t0 < ta:
+            time.sleep(0.0005)
+        tickets.append(Ticket(ctx, p, o))
+        log("%s request %d/%d submitted at %.2f s" % (tag, len(tickets), len(reqs), ta))
+    vals = []
+    for i, t in enumerate(tickets):
+        vals.append(t.value())
+        log("%s request %d/%d done, latency %.2f s" % (tag, i + 1, len(reqs),
+                                                      vals[-1]["t_end"] - vals[-1]["t_submit"]))
+    return vals, time.perf_counter() - t0
+
+
+def stream_summary(reqs, vals, dt, flops):
+    import numpy as np
+
+    lat = np.array([v["t_end"] - v["t_submit"] for v in vals])
+    wait = np.array([v["t_start"] - v["t_submit"] for v in vals])
+    return {
+        "steps_per_s": sum(o.n_steps for _, o in reqs) / dt,
+        "tflops": sum(flops) / dt / 1e12,
+        "latency_p50_s": float(np.percentile(lat, 50)),
+        "latency_p99_s": float(np.percentile(lat, 99)),
+        "queue_wait_p50_s": float(np.percentile(wait, 50)),
+        "queue_wait_p99_s": float(np.percentile(wait, 99)),
+        "fp64_reruns": sum(1 for v, (_, o) in zip(vals, reqs) if v["prec_used"] != o.prec),
+    }
+
+
+def run_serve_bench(args):
     from paper_2306_00358_amd import Context, Ticket
     from paper_2306_00358_amd.flops import dims_schedule, step_flops
 
     reqs = serve_requests(args.serve, seed=0)
+    loads = [float(x) for x in args.serve_loads.split(",") if x.strip()]
+    if not loads or min(loads) <= 0.0:
+        raise SystemExit("--serve-loads needs positive fractions of the saturation rate")
 
     def d0(p):
         return 2 if p.model == 0 else 2 * p.n_max + 1
@@ -211,31 +263,20 @@ def run_serve_bench(args):
             t.value()
             log("closed-loop request %d/%d done" % (i + 1, n_pre))
         sat = n_pre / (time.perf_counter() - t0)
-        rate = 0.8 * sat
-        arrivals = np.cumsum(np.random.default_rng(1).exponential(1.0 / rate, size=len(reqs)))
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        tickets = []
-        for (p, o), ta in zip(reqs, arrivals):
-            while time.perf_counter() - t0 < ta:
-                time.sleep(0.0005)
-            tickets.append(Ticket(ctx, p, o))
-            log("request %d/%d submitted at %.2f s" % (len(tickets), len(reqs), ta))
-        vals = []
-        for i, t in enumerate(tickets):
-            vals.append(t.value())
-            log("request %d/%d done, latency %.2f s" % (i + 1, len(reqs),
-                                                       vals[-1]["t_end"] - vals[-1]["t_submit"]))
-        dt = time.perf_counter() - t0
+        rate = loads[0] * sat
+        vals, dt = serve_stream(ctx, reqs, rate, 1, "load %.2f" % loads[0])
         stats = ctx.sched_stats()
         k = min(len(reqs), args.serve_check_max) if args.serve_check else 0
         errors = serve_errors(ctx, reqs[:k], vals[:k]) if k else None
-    lat = np.array([v["t_end"] - v["t_submit"] for v in vals])
-    wait = np.array([v["t_start"] - v["t_submit"] for v in vals])
-    n_dir = sum(o.n_steps for _, o in reqs)
+        sweep = []
+        for j, load in enumerate(loads[1:]):
+            v2, dt2 = serve_stream(ctx, reqs, load * sat, 2 + j, "load %.2f" % load)
+            sweep.append(dict(load=load, arrival_rate_per_s=load * sat,
+                              **stream_summary(reqs, v2, dt2, flops)))
+    main = stream_summary(reqs, vals, dt, flops)
     out = {
         "metric": METRIC + " [serving]",
-        "value": n_dir / dt,
+        "value": main["steps_per_s"],
         "unit": "steps/s",
         "n_gpus": 1, "steps": len(reqs), "warmup": n_pre,
         "ms_per_step": dt / len(reqs) * 1e3,
@@ -243,18 +284,20 @@ def run_serve_bench(args):
         "dtype": "fp32/bf16x3", "data": "synthetic",
         "config": {"workload": "seeded Poisson stream of %d Ising/XY requests, D_cut in "
                                "{16..80}, 20-40 steps" % len(reqs),
-                   "workers": args.workers, "arrival_rate_per_s": rate,
+                   "workers": args.workers, "load": loads[0], "arrival_rate_per_s": rate,
                    "saturation_rate_per_s": sat},
-        "tflops": sum(flops) / dt / 1e12,
-        "latency_p50_s": float(np.percentile(lat, 50)),
-        "latency_p99_s": float(np.percentile(lat, 99)),
-        "queue_wait_p50_s": float(np.percentile(wait, 50)),
-        "queue_wait_p99_s": float(np.percentile(wait, 99)),
+        "tflops": main["tflops"],
+        "latency_p50_s": main["latency_p50_s"],
+        "latency_p99_s": main["latency_p99_s"],
+        "queue_wait_p50_s": main["queue_wait_p50_s"],
+        "queue_wait_p99_s": main["queue_wait_p99_s"],
         "admission": stats,
-        "fp64_reruns": sum(1 for v, (_, o) in zip(vals, reqs) if v["prec_used"] != o.prec),
+        "fp64_reruns": main["fp64_reruns"],
         "lnz_rel_error_vs_fp64": errors,
         "lnz_error_checked_requests": k,
     }
+    if sweep:
+        out["load_sweep"] = sweep
     print(json.dumps(out), flush=True)
 
 
