@@ -29,6 +29,8 @@
 // n >= N are loaded from clamped (valid) addresses and never stored.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "internal.h"
 
 namespace hotrg {
@@ -130,18 +132,117 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm_f64_lds(
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
-  auto issue = [&](int k0, int stage) {
+  auto issue_a = [&](int k0, int stage) {
+    load_kcontig<BM, BK, NW>(A, lda, m0, M, k0, smem + stage * STAGE, wave, lane);
+  };
+  auto issue_b = [&](int k0, int stage) {
     char* base = smem + stage * STAGE;
-    load_kcontig<BM, BK, NW>(A, lda, m0, M, k0, base, wave, lane);
     if (BL == B_NCONTIG)
       load_ncontig<BK, BN, NW>(B, ldb, k0, n0, N, base + A_BYTES, wave, lane);
     else
       load_kcontig<BN, BK, NW>(B, ldb, n0, N, k0, base + A_BYTES, wave, lane);
   };
+  auto issue = [&](int k0, int stage) {
+    issue_a(k0, stage);
+    issue_b(k0, stage);
+  };
 
   const int nslab = K / BK;
   issue(0, 0);
   if (NST == 3 && nslab > 1) issue(BK, 1);
+  if constexpr (NST == 3 && BL == B_NCONTIG) {
+    // Software-pipelined across slabs: the barrier into slab s+1 and the
+    // reads of its first fragments come before the MFMAs of slab s's last k
+    // step, so both waves of a SIMD still have MFMAs to issue while the
+    // barrier and the LDS reads complete.
+    auto read_a = [&](int stage, double (&a)[4][KQ]) {
+      const char* as = smem + stage * STAGE;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = wm * 64 + i * 16 + li;
+#pragma unroll
+        for (int u = 0; u < KQ / 2; ++u) {
+          const int c = lg * (KQ / 2) + u;
+          const d2 v = *(const d2*)(as + (r * CH + (c ^ swz<BK>(r))) * 16);
+          a[i][2 * u] = v.x;
+          a[i][2 * u + 1] = v.y;
+        }
+      }
+    };
+    auto read_b = [&](int stage, int t, double (&b)[4]) {
+      const char* bs = smem + stage * STAGE + A_BYTES;
+      const int k = lg * KQ + t;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = *(const double*)(bs + (k * BN + wn * 64 + j * 16 + li) * 8);
+    };
+    // slab 0: this wave's copies (slab 1's may be pending), then everyone's
+    if (nslab > 1)
+      asm volatile("s_waitcnt vmcnt(%0)" ::"n"(LOADS) : "memory");
+    else
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    double a[4][KQ], b[4];
+    read_a(0, a);
+    read_b(0, 0, b);
+    // one slab; PRE: copies of slab s+2 go out during it, CROSS: slab s+1
+    // follows (compile-time flags, so the main loop body has no branches
+    // and the compiler can interleave the LDS reads with the MFMAs)
+    auto slab = [&](int s, auto pre_c, auto cross_c) {
+      constexpr bool PRE = decltype(pre_c)::value;
+      constexpr bool CROSS = decltype(cross_c)::value;
+      const int cur = s % 3;
+      double an[4][KQ];
+#pragma unroll
+      for (int t = 0; t < KQ; ++t) {
+        double bn[4];
+        if (t + 1 < KQ) {
+          read_b(cur, t + 1, bn);
+        } else if constexpr (CROSS) {
+          // this wave's copies of slab s+1 have landed (those of s+2 may be
+          // pending) and its reads of slab s have returned; after the
+          // barrier every wave's have, so slab s+1 may be read and, during
+          // it, the stage of slab s refilled
+          if constexpr (PRE)
+            asm volatile("s_waitcnt vmcnt(%0)" ::"n"(LOADS) : "memory");
+          else
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+          asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+          __builtin_amdgcn_s_barrier();
+          asm volatile("" ::: "memory");
+          read_a((s + 1) % 3, an);
+          read_b((s + 1) % 3, 0, bn);
+        }
+        // slab s+2 goes to the stage slab s-1 held, free since the barrier
+        // that opened slab s
+        if constexpr (PRE) {
+          if (t == 0) issue_a((s + 2) * BK, (s + 2) % 3);
+          if (t == 1) issue_b((s + 2) * BK, (s + 2) % 3);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i][t], b[j], acc[i][j], 0, 0, 0);
+        if (t + 1 < KQ || CROSS) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) b[j] = bn[j];
+        }
+      }
+      if constexpr (CROSS) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int u = 0; u < KQ; ++u) a[i][u] = an[i][u];
+      }
+    };
+    using yes = std::integral_constant<bool, true>;
+    using no = std::integral_constant<bool, false>;
+    int s = 0;
+    for (; s + 2 < nslab; ++s) slab(s, yes{}, yes{});
+    if (s + 1 < nslab) slab(s++, no{}, yes{});
+    if (s < nslab) slab(s, no{}, no{});
+  } else
   for (int s = 0; s < nslab; ++s) {
     const int cur = NST == 2 ? (s & 1) : s % 3;
     if (NST == 2) {
@@ -164,7 +265,10 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm_f64_lds(
     // every wave has also finished reading slab s-1, whose stage takes s+2
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");  // no LDS access moves above the barrier
-    if (NST == 3 && s + 2 < nslab) issue((s + 2) * BK, (s + 2) % 3);
+    // with three stages the copies of slab s+2 go out from inside the MFMA
+    // sequence below (A after the first k step's reads, B after the
+    // second's), so that both waves of a SIMD have MFMAs to issue meanwhile
+    const bool pre = NST == 3 && s + 2 < nslab;
     const char* as = smem + cur * STAGE;
     const char* bs = as + A_BYTES;
     // A values of this lane for the slab: rows wm*64 + i*16 + li, k in [lg*KQ, lg*KQ + KQ)
@@ -187,6 +291,8 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm_f64_lds(
         double b[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) b[j] = *(const double*)(bs + (k * BN + wn * 64 + j * 16 + li) * 8);
+        if (pre && t == 0) issue_a((s + 2) * BK, (s + 2) % 3);
+        if (pre && t == 1) issue_b((s + 2) * BK, (s + 2) % 3);
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -207,12 +313,15 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm_f64_lds(
         }
       }
 #pragma unroll
-      for (int t = 0; t < KQ; ++t)
+      for (int t = 0; t < KQ; ++t) {
+        if (pre && t == 1) issue_a((s + 2) * BK, (s + 2) % 3);
+        if (pre && t == 2) issue_b((s + 2) * BK, (s + 2) % 3);
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
           for (int j = 0; j < 4; ++j)
             acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i][t], b[j][t], acc[i][j], 0, 0, 0);
+      }
     }
     // all LDS reads of this stage have returned before any wave refills it
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
