@@ -28,6 +28,8 @@
 // one k per MFMA; for BF16 group g owns the same 8 k in one MFMA.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include <cstdlib>
 
 #include "internal.h"
@@ -122,6 +124,99 @@ __global__ __launch_bounds__(512) void k_gemm_rp(const void* __restrict__ Ahi,
   const int nslab = K / 32;
   issue(0, 0);
   if (NST == 3 && nslab > 1) issue(32, 1);
+  // a slab's fragments: rows of A (hi/lo or the two f32 halves), columns of B
+  struct Frag {
+    f4 a0[TM], a1[TM], b0[4], b1[4];
+  };
+  auto read_frag = [&](int stage, Frag& f) {
+    const char* as = smem + stage * STAGE;
+    const char* bs = as + A_BYTES;
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      const int r = wm * 16 * TM + i * 16 + li;
+      f.a0[i] = *(const f4*)(as + r * 128 + ((c0 ^ rp_swz(r)) << 4));
+      f.a1[i] = *(const f4*)(as + r * 128 + ((c1 ^ rp_swz(r)) << 4));
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r = wn * 64 + j * 16 + li;
+      f.b0[j] = *(const f4*)(bs + r * 128 + ((c0 ^ rp_swz(r)) << 4));
+      f.b1[j] = *(const f4*)(bs + r * 128 + ((c1 ^ rp_swz(r)) << 4));
+    }
+  };
+  // the MFMAs of row tile i of a slab
+  auto mfma_row = [&](int i, const Frag& f) {
+    if (MODE == RP_F32) {
+#pragma unroll
+      for (int t = 0; t < 8; ++t)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const float av = t < 4 ? f.a0[i][t] : f.a1[i][t - 4];
+          const float bv = t < 4 ? f.b0[j][t] : f.b1[j][t - 4];
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[i][j], 0, 0, 0);
+        }
+    } else {
+      const bf8 ah = __builtin_bit_cast(bf8, f.a0[i]);
+      const bf8 al = __builtin_bit_cast(bf8, f.a1[i]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const bf8 bh = __builtin_bit_cast(bf8, f.b0[j]);
+        const bf8 bl = __builtin_bit_cast(bf8, f.b1[j]);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[i][j], 0, 0, 0);
+      }
+    }
+  };
+  if constexpr (NST == 3) {
+    // Software-pipelined across slabs (one barrier per slab): the barrier
+    // into slab s+1 and the reads of its fragments come before the MFMAs of
+    // the second half of slab s's row tiles.  PRE: copies of slab s+2 go
+    // out during slab s; CROSS: slab s+1 follows (compile-time flags, so the
+    // main loop body has no branches).
+    if (nslab > 1)
+      asm volatile("s_waitcnt vmcnt(%0)" ::"n"(LOADS) : "memory");
+    else
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    Frag cur;
+    read_frag(0, cur);
+    auto slab = [&](int s, auto pre_c, auto cross_c) {
+      constexpr bool PRE = decltype(pre_c)::value;
+      constexpr bool CROSS = decltype(cross_c)::value;
+      // slab s+2 goes to the stage slab s-1 held, free since the barrier
+      // that opened slab s
+      if constexpr (PRE) issue((s + 2) * 32, (s + 2) % 3);
+      Frag nxt;
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        if constexpr (CROSS) {
+          if (i == TM / 2) {
+            // this wave's copies of slab s+1 have landed (those of s+2 may
+            // be pending) and its reads of slab s have returned; after the
+            // barrier every wave's have
+            if constexpr (PRE)
+              asm volatile("s_waitcnt vmcnt(%0)" ::"n"(LOADS) : "memory");
+            else
+              asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+            __builtin_amdgcn_s_barrier();
+            asm volatile("" ::: "memory");
+            read_frag((s + 1) % 3, nxt);
+          }
+        }
+        mfma_row(i, cur);
+      }
+      if constexpr (CROSS) cur = nxt;
+    };
+    using yes = std::integral_constant<bool, true>;
+    using no = std::integral_constant<bool, false>;
+    int s = 0;
+    for (; s + 2 < nslab; ++s) slab(s, yes{}, yes{});
+    if (s + 1 < nslab) slab(s++, no{}, yes{});
+    if (s < nslab) slab(s, no{}, no{});
+  } else
   for (int s = 0; s < nslab; ++s) {
     const int cur = NST == 2 ? (s & 1) : s % 3;
     if (NST == 2 && s + 1 < nslab) {

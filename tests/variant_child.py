@@ -1,0 +1,65 @@
+"""Child process of `test_gpu_kernel_variants.py`: the coarse contraction and
+the environment at shapes that reach the large-GEMM kernels, with whatever
+kernel the environment variables of this process force, against the FP64
+oracle.  FP64: element-wise within 1e-12 of the largest output.  FP32 /
+split BF16: the element-wise bounds of `test_gpu_precision.py`.  Exits
+non-zero on the first violation."""
+
+import sys
+
+import numpy as np
+import torch
+
+from oracle import hotrg
+from paper_2306_00358_amd import Context, hotrg_coarse, hotrg_environment
+from tests.inputs import random_projector, random_tensor
+
+U24, U16 = 2.0**-24, 2.0**-16
+EP = {"fp32": U24, "bf16x3": 3 * U16}
+STORE = {"fp32": U24, "bf16x3": U16}
+
+
+def gpu(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def check(name, got, want, scale, bound):
+    err = np.abs(got - want)
+    worst = float((err / scale).max())
+    print("%s max err/scale %.3e bound %.3e" % (name, worst, bound), flush=True)
+    if not np.all(err <= bound * scale):
+        sys.exit("%s: bound exceeded" % name)
+
+
+def main(prec):
+    with Context(0) as ctx:
+        for dx, dy, dn in [(24, 24, 24), (32, 32, 32)]:
+            T = random_tensor(dx, dy, seed=700 + dx + dy)
+            U = random_projector(dx, dn, seed=800 + dn)
+            want = hotrg.coarse_tensor(T, U)
+            Tt = torch.empty((dn, dy, dn, dy), dtype=torch.float64, device="cuda")
+            hotrg_coarse(ctx, gpu(T), gpu(U), Tt, prec=prec)
+            if prec == "fp64":
+                scale, bound = np.abs(want).max(), 1e-12
+            else:
+                scale = hotrg.coarse_tensor(np.abs(T), np.abs(U))
+                bound = (3 * EP[prec] + (dx + dx * dy + dx * dx) * U24 + 2 * STORE[prec]
+                         + (4 * U24 if prec == "fp32" else 0))
+            check("coarse %d %d %d" % (dx, dy, dn), Tt.cpu().numpy(), want, scale, bound)
+        for dx, dy in [(32, 32), (32, 4)]:
+            T = random_tensor(dx, dy, seed=900 + dx + dy)
+            want = hotrg.environment(T)
+            M = torch.empty((dx * dx, dx * dx), dtype=torch.float64, device="cuda")
+            hotrg_environment(ctx, gpu(T), M, prec=prec)
+            if prec == "fp64":
+                scale, bound = np.abs(want).max(), 1e-12
+            else:
+                scale = hotrg.environment(np.abs(T))
+                bound = (2 * EP[prec] + (dx * dy + dy * dy) * U24 + STORE[prec]
+                         + (4 * U24 if prec == "fp32" else 0))
+            check("environment %d %d" % (dx, dy), M.cpu().numpy(), want, scale, bound)
+    print("ok", flush=True)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1])
