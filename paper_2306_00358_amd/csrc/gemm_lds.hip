@@ -207,7 +207,9 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm_f64_lds(
             asm volatile("s_waitcnt vmcnt(%0)" ::"n"(LOADS) : "memory");
           else
             asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-          asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+          // lgkmcnt(0) as the builtin (vmcnt and expcnt left at their
+          // maximum), which the compiler's own wait insertion accounts for
+          __builtin_amdgcn_s_waitcnt(0xC07F);
           __builtin_amdgcn_s_barrier();
           asm volatile("" ::: "memory");
           read_a((s + 1) % 3, an);
