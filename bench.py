@@ -46,7 +46,7 @@ DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}
 # FETCH_SIZE / WRITE_SIZE counter runs of `bench.py --kernel-probe` (scaled by
 # the readings of a 1 GiB copy); the summary and commands are under profiles/.
 # An entry is valid only for the kernel version it was measured on.
-TRAFFIC = {("fp64", 64): 1.0478e11}
+TRAFFIC = {("fp64", 64): 9.648e10}
 
 
 def parse():
