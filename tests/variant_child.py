@@ -33,7 +33,9 @@ def check(name, got, want, scale, bound):
 
 def main(prec):
     with Context(0) as ctx:
-        for dx, dy, dn in [(24, 24, 24), (32, 32, 32)]:
+        # C1 has K = dx: (16, 32, 16) gives one 16-deep slab, (32, 32, 32) two
+        # (one 32-deep), (64, 4, 16) four (two 32-deep); C2 has K = dx * dy
+        for dx, dy, dn in [(24, 24, 24), (32, 32, 32), (16, 32, 16), (64, 4, 16)]:
             T = random_tensor(dx, dy, seed=700 + dx + dy)
             U = random_projector(dx, dn, seed=800 + dn)
             want = hotrg.coarse_tensor(T, U)
