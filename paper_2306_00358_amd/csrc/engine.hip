@@ -245,12 +245,17 @@ void environment_f64(hotrg_ctx* c, const double* Tn, const double* Xt, int dx, i
   ensure(c, Mb, (size_t)(n * n) * 8);
   // A2[(i,e),(k,f)] = sum_{c,d} T[i,e,c,d] T[k,f,c,d], stored as A2'[(i,k),(e,f)]
   // rows (i,e): i -> dx*dy^2, e -> dy; cols (k,f): k -> dy^2, f -> 1
-  const OutMap o2 = omap2(dy, dx * K2, dy, dy, K2, 1);
-  gemm_f64(Tn, P, Tn, P, B_KCONTIG, (double*)c->A2.p, o2, (int)P, (int)P, (int)P, nullptr,
-           c->stream, GEMM_TAG_ENV);
   // A1[(j,e),(l,f)] = sum_{a,b} T[j,a,b,e] T[l,a,b,f] from Xt[(l,d),(u,r)], stored as A1'[(j,l),(e,f)]
-  gemm_f64(Xt, P, Xt, P, B_KCONTIG, (double*)c->A1.p, o2, (int)P, (int)P, (int)P, nullptr,
-           c->stream, GEMM_TAG_ENV);
+  // Both halves are Gram matrices X X^T: where it applies, one launch
+  // computes the upper triangles of both and mirrors them (half the MFMAs).
+  const OutMap o2 = omap2(dy, dx * K2, dy, dy, K2, 1);
+  if (!gemm_f64_syrk(Tn, P, (double*)c->A2.p, o2, (int)P, (int)P, c->stream, Xt,
+                     (double*)c->A1.p)) {
+    gemm_f64(Tn, P, Tn, P, B_KCONTIG, (double*)c->A2.p, o2, (int)P, (int)P, (int)P, nullptr,
+             c->stream, GEMM_TAG_ENV);
+    gemm_f64(Xt, P, Xt, P, B_KCONTIG, (double*)c->A1.p, o2, (int)P, (int)P, (int)P, nullptr,
+             c->stream, GEMM_TAG_ENV);
+  }
   // M[(i,j),(k,l)] = sum_{e,f} A2'[(i,k),(e,f)] A1'[(j,l),(e,f)]: GEMM rows (i,k), cols (j,l)
   // rows (i,k): i -> dx*n, k -> dx; cols (j,l): j -> n, l -> 1
   const OutMap om = omap2(dx, dx * n, dx, dx, n, 1);

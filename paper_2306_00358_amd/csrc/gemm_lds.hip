@@ -11,7 +11,15 @@
 // the slab s+1 copy is in flight while slab s is multiplied, with a barrier
 // after the copy lands and one before the stage is refilled.  Three stages:
 // slabs s+1 and s+2 are in flight; one barrier per slab both publishes slab
-// s and frees the stage of slab s-1 for the copy of slab s+2.
+// s and frees the stage of slab s-1 for the copy of slab s+2.  With an
+// N-contiguous B the three-stage loop is also software-pipelined across
+// slabs (copies issued from inside the MFMA sequence, the barrier into the
+// next slab and its first fragment reads among this slab's MFMAs).
+//
+// Symmetric mode (sym, for Gram matrices C = A A^T): a 1-D grid over the
+// tiles that reach the upper triangle; each element m <= n is stored at
+// (m, n) and, for m < n, at (n, m) -- the same products summed in the same
+// order as the full product's element (n, m), for about half the MFMAs.
 //
 // LDS layout.  Operand rows that are K-contiguous in global memory (A, and B
 // when K-contiguous) are stored as rows of BK doubles cut into 16-byte
@@ -105,7 +113,8 @@ __device__ __forceinline__ void load_ncontig(const double* __restrict__ G, long 
 template <int WGM, int WGN, int BK, int BL, int TAG, int NST>
 __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm_f64_lds(
     const double* __restrict__ A, long long lda, const double* __restrict__ B, long long ldb,
-    double* __restrict__ C, OutMap om, int M, int N, int K, unsigned long long* maxbits) {
+    double* __restrict__ C, OutMap om, int M, int N, int K, unsigned long long* maxbits,
+    int sym, const double* __restrict__ A_2, double* __restrict__ C_2) {
   constexpr int NW = WGM * WGN;
   constexpr int BM = 64 * WGM, BN = 64 * WGN;
   constexpr int CH = BK / 2;
@@ -123,7 +132,34 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm_f64_lds(
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wm = wave / WGN, wn = wave % WGN;
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  // sym (C = A A^T, M = N, B = A): the 1-D grid enumerates, row tile by row
+  // tile, the tiles that reach the upper triangle (n >= m somewhere); row
+  // tile bm starts at column tile bm*BM/BN, and every row tile has at least
+  // one, so the walk ends inside the grid the host computed the same way
+  // With sym == 2 the grid holds two such products of the same shape, the
+  // second on A_2 into C_2, one after the other.
+  int bm = blockIdx.y, bn = blockIdx.x;
+  if (sym) {
+    const int nbn = (N + BN - 1) / BN;
+    int rem = blockIdx.x;
+    if (sym == 2) {
+      int tiles = 0;
+      for (int r = 0; r * BM < M; ++r) tiles += nbn - r * BM / BN;
+      if (rem >= tiles) {
+        rem -= tiles;
+        A = A_2;
+        B = A_2;
+        C = C_2;
+      }
+    }
+    bm = 0;
+    while (rem >= nbn - bm * BM / BN) {
+      rem -= nbn - bm * BM / BN;
+      ++bm;
+    }
+    bn = bm * BM / BN + rem;
+  }
+  const int m0 = bm * BM, n0 = bn * BN;
   const int li = lane & 15, lg = lane >> 4;
 
   d4 acc[4][4];
@@ -336,9 +372,11 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm_f64_lds(
   double mx = 0.0;
   long long coff[4];
   bool cok[4];
+  int ncol[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int n = n0 + wn * 64 + j * 16 + li;
+    ncol[j] = n;
     cok[j] = n < N;
     coff[j] = cok[j] ? lmap_col(om, n) : 0;
   }
@@ -349,10 +387,16 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm_f64_lds(
       const int m = m0 + wm * 64 + i * 16 + lg + 4 * v;
       if (m >= M) continue;
       const long long roff = lmap_row(om, m);
+      const long long moff = sym ? lmap_col(om, m) : 0;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         if (!cok[j]) continue;
         const double x = acc[i][j][v];
+        if (sym) {
+          // the upper triangle, and its mirror image (same products, same order)
+          if (m > ncol[j]) continue;
+          if (m < ncol[j]) C[lmap_row(om, ncol[j]) + moff] = x;
+        }
         C[roff + coff[j]] = x;
         mx = fmax(mx, fabs(x));
       }
@@ -367,16 +411,24 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm_f64_lds(
 template <int WGM, int WGN, int BK, int TAG, int NST = 2>
 static void launch_lds(const double* A, long long lda, const double* B, long long ldb, int bl,
                        double* C, const OutMap& om, int M, int N, int K,
-                       unsigned long long* maxbits, hipStream_t s) {
+                       unsigned long long* maxbits, hipStream_t s, int sym = 0,
+                       const double* A_2 = nullptr, double* C_2 = nullptr) {
   constexpr int BM = 64 * WGM, BN = 64 * WGN;
   dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM);
+  if (sym) {
+    // tiles reaching the upper triangle: row tile bm from column tile bm*BM/BN on
+    const int nbn = (N + BN - 1) / BN;
+    int tiles = 0;
+    for (int bm = 0; bm * BM < M; ++bm) tiles += nbn - bm * BM / BN;
+    grid = dim3(sym == 2 ? 2 * tiles : tiles, 1);
+  }
   dim3 block(64 * WGM * WGN);
   if (bl == B_NCONTIG)
     hipLaunchKernelGGL((k_gemm_f64_lds<WGM, WGN, BK, B_NCONTIG, TAG, NST>), grid, block, 0, s, A,
-                       lda, B, ldb, C, om, M, N, K, maxbits);
+                       lda, B, ldb, C, om, M, N, K, maxbits, sym, A_2, C_2);
   else
     hipLaunchKernelGGL((k_gemm_f64_lds<WGM, WGN, BK, B_KCONTIG, TAG, NST>), grid, block, 0, s, A,
-                       lda, B, ldb, C, om, M, N, K, maxbits);
+                       lda, B, ldb, C, om, M, N, K, maxbits, sym, A_2, C_2);
 }
 
 // Returns false when the operands do not meet the requirements above.
@@ -419,6 +471,24 @@ bool gemm_f64_lds(const double* A, long long lda, const double* B, long long ldb
     else
       launch_lds<2, 2, 32, GEMM_TAG_OTHER>(A, lda, B, ldb, blayout, C, om, M, N, K, maxbits, s);
   }
+  return true;
+}
+
+// C = A A^T for an M x K K-contiguous A (M = N): the tiles that reach the
+// upper triangle, each element written also at its mirror position; the
+// same products are summed in the same order as the full product.  Returns
+// false where the LDS kernel does not apply (the caller then runs the full
+// product).
+// With A_2 and C_2 given, C_2 = A_2 A_2^T (same shape, strides and map) in
+// the same launch: the half-size grids of the two products together balance
+// better over the CUs than each alone (at M = 4096 with 256 x 128 tiles, 544
+// tiles in three rounds of 256 workgroups instead of two rounds each).
+bool gemm_f64_syrk(const double* A, long long lda, double* C, const OutMap& om, int M, int K,
+                   hipStream_t s, const double* A_2, double* C_2) {
+  if (M < 128 || (long long)M * M < (1LL << 20) || K < 16 || K % 16 != 0) return false;
+  if ((lda & 1) || ((uintptr_t)A & 15) || ((uintptr_t)A_2 & 15)) return false;
+  launch_lds<4, 2, 16, GEMM_TAG_ENV, 3>(A, lda, A, lda, B_KCONTIG, C, om, M, M, K, nullptr, s,
+                                        A_2 ? 2 : 1, A_2, C_2);
   return true;
 }
 

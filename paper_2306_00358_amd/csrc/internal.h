@@ -59,6 +59,11 @@ void gemm_f64_splitk(const double* A, long long lda, const double* B, long long 
 // Direct-to-LDS FP64 GEMM (gemm_lds.hip); returns false if the operands do
 // not meet its alignment / K-multiple requirements.  variant 0: 4 waves,
 // 128 x 128 tile, K slab 32; variant 1: 8 waves, 256 x 128 tile, K slab 16.
+// C = A A^T (M x M, A M x K K-contiguous) from the upper-triangle tiles with
+// mirrored stores, and C_2 = A_2 A_2^T in the same launch when A_2 is given;
+// false where it does not apply.
+bool gemm_f64_syrk(const double* A, long long lda, double* C, const OutMap& om, int M, int K,
+                   hipStream_t s, const double* A_2 = nullptr, double* C_2 = nullptr);
 bool gemm_f64_lds(const double* A, long long lda, const double* B, long long ldb, int blayout,
                   double* C, const OutMap& om, int M, int N, int K, unsigned long long* maxbits,
                   hipStream_t s, int tag, int variant);
