@@ -72,7 +72,7 @@ def parse():
                     help="comma-separated arrival rates as fractions of the measured "
                          "saturation rate; the stream at the first one is the result, "
                          "the others are reported under load_sweep")
-    ap.add_argument("--workers", type=int, default=8)
+    ap.add_argument("--workers", type=int, default=16)
     ap.add_argument("--kernel-probe", action="store_true",
                     help="run one coarse contraction at the benchmark shape and a 1 GiB "
                          "calibration copy (for hardware-counter runs), then exit")

@@ -193,7 +193,7 @@ hotrg_status hotrg_run(hotrg_ctx* ctx, const hotrg_model_params* params, const h
  * which precision produced the result.
  * submit/poll/wait/cancel are thread-safe. */
 
-/* Worker count (default 8); takes effect before the first submit or batch. */
+/* Worker count (default 16); takes effect before the first submit or batch. */
 hotrg_status hotrg_ctx_set_workers(hotrg_ctx* ctx, int n_workers);
 
 /* Queue one problem.  `result` is caller-owned and must stay valid (with its

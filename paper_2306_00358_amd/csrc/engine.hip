@@ -86,7 +86,7 @@ struct hotrg_ctx {
   double last_eig_resid = 0.0;
   // many-problem scheduler (sched.cpp), created on first use
   void* sched = nullptr;
-  int n_workers = 8;
+  int n_workers = 16;
   std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
   // per-phase timing
   bool timing = false;
