@@ -380,7 +380,7 @@ static void launch_big(const double* A, long long lda, const double* B, long lon
 // forces one kernel.
 namespace {
 
-enum { C_LDS2 = 0, C_LDS3, C_LDS32, C_LDS_HALF, C_BIG, C_G128, C_G64, C_COUNT };
+enum { C_LDS2 = 0, C_LDS3, C_LDS32, C_LDS_HALF, C_LDS_N64, C_BIG, C_G128, C_G64, C_COUNT };
 
 struct TuneKey {
   long long v[16];
@@ -475,6 +475,8 @@ void gemm_f64(const double* A, long long lda, const double* B, long long ldb, in
         return N >= 128 && gemm_f64_lds(A, lda, B, ldb, blayout, C, om, M, N, K, maxbits, s, tag, 0);
       case C_LDS_HALF:
         return N >= 128 && gemm_f64_lds(A, lda, B, ldb, blayout, C, om, M, N, K, maxbits, s, tag, 4);
+      case C_LDS_N64:
+        return N <= 64 && gemm_f64_lds(A, lda, B, ldb, blayout, C, om, M, N, K, maxbits, s, tag, 5);
       case C_BIG:
         if (N < 128 || K < 64) return false;
         switch (tag) {
@@ -508,8 +510,8 @@ void gemm_f64(const double* A, long long lda, const double* B, long long ldb, in
   // fixed rule: 256 x 128 tiles, three LDS stages for long K (one barrier per
   // slab, two slabs in flight), two for short K
   const int variant = forced >= 0 ? forced : (K >= 256 ? 3 : 1);
-  if ((long long)M * N >= (1LL << 20) && N >= 128 && variant != 2 &&
-      gemm_f64_lds(A, lda, B, ldb, blayout, C, om, M, N, K, maxbits, s, tag, variant))
+  if ((long long)M * N >= (1LL << 20) && (N >= 128 || (variant == 5 && N <= 64)) &&
+      variant != 2 && gemm_f64_lds(A, lda, B, ldb, blayout, C, om, M, N, K, maxbits, s, tag, variant))
     return;
   if ((long long)M * N >= (1LL << 22) && N >= 128 && K >= 64) {
     cand(C_BIG);

@@ -110,6 +110,24 @@ __device__ __forceinline__ void load_ncontig(const double* __restrict__ G, long 
   }
 }
 
+// Copy a BK x 64 slab of an N-contiguous operand: a 64-wide row is 512
+// bytes, so one wave instruction moves two rows (lanes 0-31 and 32-63).
+template <int BK, int NW>
+__device__ __forceinline__ void load_ncontig64(const double* __restrict__ G, long long ld, int k0,
+                                               int col0, int cols_valid, char* lds, int wave,
+                                               int lane) {
+  static_assert((BK / 2) % NW == 0, "row pairs must split over waves");
+#pragma unroll
+  for (int q = 0; q < BK / 2 / NW; ++q) {
+    const int pr = wave + q * NW;
+    const int r = 2 * pr + (lane >> 5);
+    int gc = col0 + 2 * (lane & 31);
+    gc = gc < cols_valid ? gc : cols_valid - 2;
+    const double* src = G + (long long)(k0 + r) * ld + gc;
+    __builtin_amdgcn_global_load_lds((const void*)src, (lds_void*)(lds + pr * 1024), 16, 0, 0);
+  }
+}
+
 template <int WGM, int WGN, int BK, int BL, int TAG, int NST>
 __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm_f64_lds(
     const double* __restrict__ A, long long lda, const double* __restrict__ B, long long ldb,
@@ -122,7 +140,8 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm_f64_lds(
   constexpr int STAGE = A_BYTES + B_BYTES;
   constexpr int KQ = BK / 4;  // k values per lane group per slab
   constexpr int A_INST = BM / (1024 / (BK * 8)) / NW;
-  constexpr int B_INST = BL == B_NCONTIG ? BK / NW : BN / (1024 / (BK * 8)) / NW;
+  constexpr int B_INST = BL == B_NCONTIG ? (BN == 64 ? BK / 2 / NW : BK / NW)
+                                          : BN / (1024 / (BK * 8)) / NW;
   constexpr int LOADS = A_INST + B_INST;  // global_load_lds per wave per slab
   static_assert(LOADS <= 63, "vmcnt range");
   static_assert(NST == 2 || NST == 3, "two or three LDS stages");
@@ -173,7 +192,9 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm_f64_lds(
   };
   auto issue_b = [&](int k0, int stage) {
     char* base = smem + stage * STAGE;
-    if (BL == B_NCONTIG)
+    if constexpr (BL == B_NCONTIG && BN == 64)
+      load_ncontig64<BK, NW>(B, ldb, k0, n0, N, base + A_BYTES, wave, lane);
+    else if constexpr (BL == B_NCONTIG)
       load_ncontig<BK, BN, NW>(B, ldb, k0, n0, N, base + A_BYTES, wave, lane);
     else
       load_kcontig<BN, BK, NW>(B, ldb, n0, N, k0, base + A_BYTES, wave, lane);
@@ -441,7 +462,16 @@ bool gemm_f64_lds(const double* A, long long lda, const double* B, long long ldb
   if (blayout == B_NCONTIG && (N & 1)) return false;
   if (((uintptr_t)A & 15) || ((uintptr_t)B & 15)) return false;
   if (blayout == B_KCONTIG && N < 1) return false;
-  if (variant == 4) {
+  if (variant == 5) {
+    // 512 x 64 tile (8 waves along M), two stages of 72 KB: products with
+    // N = 64 (the last coarse contraction), which the 128-wide tiles would pad
+    if (tag == GEMM_TAG_C2)
+      launch_lds<8, 1, 16, GEMM_TAG_C2>(A, lda, B, ldb, blayout, C, om, M, N, K, maxbits, s);
+    else if (tag == GEMM_TAG_ENV)
+      launch_lds<8, 1, 16, GEMM_TAG_ENV>(A, lda, B, ldb, blayout, C, om, M, N, K, maxbits, s);
+    else
+      launch_lds<8, 1, 16, GEMM_TAG_OTHER>(A, lda, B, ldb, blayout, C, om, M, N, K, maxbits, s);
+  } else if (variant == 4) {
     // 128 x 128 tile, 4 waves, 64 KB of LDS: two workgroups per CU
     if (tag == GEMM_TAG_C2)
       launch_lds<2, 2, 16, GEMM_TAG_C2>(A, lda, B, ldb, blayout, C, om, M, N, K, maxbits, s);

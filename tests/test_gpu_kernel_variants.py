@@ -16,10 +16,11 @@ pytestmark = pytest.mark.gpu
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 # FP64: 0 = 128 x 128 tile with 32-deep slabs, 1 = 256 x 128 with two LDS stages,
-# 3 = three stages (software-pipelined), 4 = 128 x 128 tile;
+# 3 = three stages (software-pipelined), 4 = 128 x 128 tile, 5 = 512 x 64 tile
+# (forced, it also runs the wide products, and C3 with N = 32 half-masked);
 # reduced precision: 0 = 256 x 256, 1 = 256 x 128 two stages,
 # 2 = 256 x 128 three stages (software-pipelined)
-CASES = ([("fp64", {"HOTRG_GEMM_VARIANT": v}) for v in ("0", "1", "3", "4")]
+CASES = ([("fp64", {"HOTRG_GEMM_VARIANT": v}) for v in ("0", "1", "3", "4", "5")]
          + [(p, {"HOTRG_AUTOTUNE": "0", "HOTRG_RP_CFG": c})
             for p in ("fp32", "bf16x3") for c in ("0", "1", "2")])
 
