@@ -146,3 +146,31 @@ int main(void) {
     subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o",
                     str(tmp_path / "caller"), "-L", libdir, "-lhotrg", "-Wl,-rpath," + libdir],
                    check=True)
+
+
+def test_footprint_properties():
+    # admission arithmetic (host only): more steps or a larger cut never need
+    # less memory, the two-sided isometry never less than one-sided; an
+    # unknown model is rejected.  (Reduced precision is not always smaller:
+    # its early steps run in FP64 and both sets of buffers stay allocated.)
+    import pytest
+
+    from paper_2306_00358_amd import HotrgError, hotrg_footprint, make_opts, model_params
+
+    for p in (model_params("ising", beta=0.44), model_params("xy", beta=1.0, n_max=3),
+              model_params("potts", beta=1.0, q=3)):
+        prev_cut = 0
+        for d_cut in (8, 16, 24, 32, 48):
+            prev_steps = 0
+            for n_steps in (1, 2, 4, 8, 16, 30):
+                f = hotrg_footprint(p, make_opts(d_cut, n_steps))
+                assert f >= prev_steps
+                prev_steps = f
+                two = hotrg_footprint(p, make_opts(d_cut, n_steps, isometry="two"))
+                assert two >= f
+            assert prev_steps >= prev_cut
+            prev_cut = prev_steps
+    bad = model_params("ising", beta=0.44)
+    bad.model = 99
+    with pytest.raises(HotrgError):
+        hotrg_footprint(bad, make_opts(8, 4))
