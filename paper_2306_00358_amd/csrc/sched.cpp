@@ -27,6 +27,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "admit.h"
 #include "internal.h"
 
 namespace hotrg {
@@ -37,7 +38,6 @@ namespace {
 
 using namespace hotrg;
 
-constexpr int kMaxSkips = 8;
 constexpr size_t kSolverMargin = 256ull << 20;  // rocBLAS / rocSOLVER internal workspace
 
 enum ReqState { Q_QUEUED = 0, Q_RUNNING = 1, Q_DONE = 2 };
@@ -172,33 +172,20 @@ void worker_loop(Server* S, int w) {
       for (;;) {
         if (S->stop) return;
         const size_t others = S->reserved - hold;
-        // first queued request that fits; the oldest may be passed over at
-        // most kMaxSkips times
-        auto pick = S->queue.end();
-        for (auto it = S->queue.begin(); it != S->queue.end(); ++it) {
-          const size_t f = (*it)->footprint;
-          if (others + hold + f <= S->budget) {
-            pick = it;
-            break;
-          }
-          if (others + f <= S->budget) {
-            release = true;  // fits once this worker's buffers are released: release, then pick again
-            break;
-          }
-          if (it == S->queue.begin() && (*it)->skips >= kMaxSkips) break;
+        const AdmitChoice ch = admit_choice(
+            S->queue, [](const std::shared_ptr<Request>& q) { return q->footprint; },
+            [](const std::shared_ptr<Request>& q) { return q->skips; }, others, hold, S->budget);
+        if (ch.action == ADMIT_RELEASE) {
+          release = true;  // release this worker's buffers, then decide again
+          break;
         }
-        if (release) break;
-        if (pick != S->queue.end()) {
-          if (pick != S->queue.begin()) {
+        if (ch.action == ADMIT_RUN) {
+          if (ch.index > 0) {
             ++S->queue.front()->skips;
             ++S->stalls;
           }
-          r = *pick;
-          S->queue.erase(pick);
-          break;
-        }
-        if (!S->queue.empty() && hold > 0) {
-          release = true;  // what this idle worker holds may be what is missing
+          r = S->queue[ch.index];
+          S->queue.erase(S->queue.begin() + (long)ch.index);
           break;
         }
         if (!S->queue.empty()) ++S->stalls;
