@@ -350,6 +350,31 @@ def small_case(ctx, reps=20):
             "rel_err_vs_onsager": abs(r["lnz_per_site"] - ONSAGER_TC) / ONSAGER_TC}
 
 
+def mid_case(ctx, reps=3):
+    """The D_cut = 32 configuration: Ising at T = 2.0, T_c and 2.5, 30
+    directional steps, FP64; steps/s over `reps` runs per temperature."""
+    import torch
+
+    from paper_2306_00358_amd import hotrg_run, make_opts, model_params
+
+    runs = []
+    for T in (2.0, None, 2.5):
+        beta = BETA_C if T is None else 1.0 / T
+        params = model_params("ising", beta=beta)
+        opts = make_opts(32, 30)
+        hotrg_run(ctx, params, opts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r = hotrg_run(ctx, params, opts)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        runs.append({"T": 1.0 / beta, "steps_per_s": 30 / dt, "ms_per_run": dt * 1e3,
+                     "lnz_per_site": r["lnz_per_site"]})
+    return {"workload": "Ising at T = 2.0, T_c, 2.5; D_cut=32, 30 directional steps, fp64",
+            "runs": runs}
+
+
 def cpu_baseline(d_cut):
     """The oracle on the host cores: one steady-state directional step at
     dims (d_cut, d_cut, d_cut) of the same Ising run (the warm-up steps that
@@ -490,6 +515,7 @@ def main():
     out["run_frac_of_peak"] = head["run_frac_of_peak"]
     out["eigh_share"] = head["eigh_share"]
     out["small_case"] = small_case(ctx)
+    out["mid_case"] = mid_case(ctx)
     if not args.no_compare:
         # the same workload with reduced-precision contractions (eigensolver
         # and log-norm stay FP64)
@@ -507,6 +533,8 @@ def main():
         out["mixed_vs_" + args.prec] = mixed
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.d_cut)
+        # the oracle at the D_cut = 32 configuration too (one steady step)
+        out["cpu_baseline"]["d_cut_32"] = cpu_baseline(32)
     print(json.dumps(out), flush=True)
     ctx.close()
 

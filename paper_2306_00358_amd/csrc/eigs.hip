@@ -12,10 +12,14 @@
 //             V = orth(Y) by shifted Cholesky-QR (Fukaya et al., "Shifted
 //             Cholesky QR for computing the QR factorization of
 //             ill-conditioned matrices", SIAM J. Sci. Comput. 42 (2020)):
-//             G = Y Y^T + s I, G = R^T R, V = R^-T Y; the first pass factors
-//             the diagonally scaled G with s = 11 (n p + p(p+1)) u trace,
-//             the next ones s = 0.  Before a check three passes make V
-//             orthonormal to rounding.  Between checks V only has to stay a
+//             G = Y Y^T + s I, G = R^T R, V = R^-T Y; the first two passes
+//             factor the diagonally scaled G with s = 11 (n p + p(p+1)) u
+//             trace, the third with s = 0.  (When M's spectrum falls to
+//             rounding noise within the block -- deep in an ordered phase --
+//             one shifted pass leaves a basis too ill-conditioned for an
+//             unshifted Cholesky; a second shifted pass brings it within
+//             reach, and the third restores orthonormality to rounding.)
+//             Before a check all three passes run.  Between checks V only has to stay a
 //             well-conditioned basis of the same span: one pass after the
 //             first, which the device leaves out (R^-1 = I) when G is
 //             already the identity to 1e-2 -- after the first pass it is
@@ -433,16 +437,17 @@ bool topk_eigs(rocblas_handle blas, const double* M, int n, int p, int need, dou
   hipLaunchKernelGGL(k_seed_block, dim3(256), dim3(256), 0, s, V, (long long)pn, 12345ULL);
 
   // one orthonormalisation of rows of Y into V: shifted Cholesky-QR of the
-  // column-scaled Gram matrix, then plain passes -- two before a
-  // Rayleigh-Ritz check (`full`), else one that is skipped on the device
-  // (R^-1 = I) when its Gram matrix is the identity to 1e-2.
+  // column-scaled Gram matrix twice, then a plain pass -- all three before a
+  // Rayleigh-Ritz check (`full`); between checks only the first two, the
+  // second skipped on the device (R^-1 = I) when its Gram matrix is the
+  // identity to 1e-2.
   auto orth = [&](const double* Yin, double* Vout, bool full) {
     const double* src = Yin;
     const int last = full ? 2 : 1;
     for (int pass = 0; pass <= last; ++pass) {
       gemm_f64_splitk(src, n, src, n, B_KCONTIG, G, p, p, p, n, kc, part, s);
       hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(kCholThreads), lds, s, G, p,
-                         pass == 0 ? shift_rel : 0.0, pass == 0 ? 1 : 0,
+                         pass < 2 ? shift_rel : 0.0, pass < 2 ? 1 : 0,
                          (pass == 0 || full) ? 0.0 : 1e-2, Rt, fail);
       double* dst = (pass == last) ? Vout : (src == T2 ? Y : T2);
       if (dst == src) dst = (src == Y) ? T2 : Y;
