@@ -56,9 +56,12 @@ typedef enum {
 } hotrg_model;
 
 typedef enum {
-  HOTRG_FP64 = 0,   /* FP64 MFMA contractions */
-  HOTRG_FP32 = 1,   /* FP32 MFMA contractions, FP32 intermediates */
-  HOTRG_BF16X3 = 2  /* split-BF16, three products, FP32 accumulation */
+  HOTRG_FP64 = 0,      /* FP64 MFMA contractions */
+  HOTRG_FP32 = 1,      /* FP32 MFMA contractions, FP32 intermediates */
+  HOTRG_BF16X3 = 2,    /* split-BF16, three products, FP32 accumulation */
+  HOTRG_PREC_AUTO = 3  /* whole runs only (hotrg_run, batch, submit): the precision
+                          with the least estimated time whose a-priori error bound
+                          (hotrg_opts.tol) is met; needs tol > 0 */
 } hotrg_precision;
 
 typedef enum {
@@ -109,6 +112,13 @@ typedef struct {
   int spec_len;       /* spectrum values recorded per step (0: none) */
   int eig;            /* hotrg_eig: how the leading eigenpairs of M are found */
   int isometry;       /* hotrg_isometry */
+  double tol;         /* reduced precision: target relative error of ln Z/N against
+                         the FP64 result (0: none).  Step k's contractions add at
+                         most C_p 2^-k to it (C_FP32 = 2e-5, C_BF16X3 = 1e-4: 2.5x the largest
+                         measured on the Ising and XY workloads; ln Z/N weighs step k by 2^-k,
+                         Sec. 2), so steps before k0 = ceil(1 + log2(C_p / tol)) keep
+                         FP64 contractions; the bound of the steps actually reduced
+                         is returned in hotrg_result.err_bound */
 } hotrg_opts;
 
 typedef struct {
@@ -134,6 +144,9 @@ typedef struct {
   int prec_used;           /* precision the result was computed with (a
                               submitted reduced-precision problem that fails
                               with HOTRG_ERR_NUMERIC is re-run once in FP64) */
+  double err_bound;        /* a-priori bound on the relative ln Z/N error against
+                              the FP64 result: C_p sum_{reduced steps k} 2^-k
+                              (0 for FP64) */
 } hotrg_result;
 
 typedef struct hotrg_ctx hotrg_ctx;
@@ -215,6 +228,14 @@ hotrg_status hotrg_cancel(hotrg_ctx* ctx, uint64_t ticket);
  * loop releases every ticket it has read, so the context's bookkeeping stays
  * bounded; hotrg_run_batch releases its own. */
 hotrg_status hotrg_release(hotrg_ctx* ctx, uint64_t ticket);
+/* The precision schedule hotrg_run would use (host arithmetic, no GPU):
+ * `prec` the precision of the reduced steps (HOTRG_PREC_AUTO resolved;
+ * HOTRG_FP64 when none), `first_reduced` the first step allowed to be
+ * reduced (steps before the steady state are FP64 regardless), `err_bound`
+ * the a-priori relative error bound of hotrg_result.err_bound.  Any output
+ * may be NULL. */
+hotrg_status hotrg_plan(const hotrg_model_params* params, const hotrg_opts* opts, int* prec,
+                        int* first_reduced, double* err_bound);
 /* Estimated peak device bytes of one problem (the admission footprint). */
 hotrg_status hotrg_footprint(const hotrg_model_params* params, const hotrg_opts* opts,
                              size_t* bytes);

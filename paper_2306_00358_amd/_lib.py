@@ -14,11 +14,11 @@ LIB_PATH = os.path.join(_PKG, "libhotrg.so")
 HOTRG_OK, HOTRG_ERR_INVALID, HOTRG_ERR_OOM, HOTRG_ERR_DEVICE, HOTRG_ERR_NUMERIC, \
     HOTRG_ERR_NOT_READY, HOTRG_ERR_CANCELLED = range(7)
 HOTRG_ISING, HOTRG_XY, HOTRG_POTTS, HOTRG_RAW, HOTRG_GXY = range(5)
-HOTRG_FP64, HOTRG_FP32, HOTRG_BF16X3 = range(3)
+HOTRG_FP64, HOTRG_FP32, HOTRG_BF16X3, HOTRG_PREC_AUTO = range(4)
 HOTRG_TRUNC_PLAIN, HOTRG_TRUNC_MULTIPLET = range(2)
 HOTRG_ISO_ONE_SIDED, HOTRG_ISO_TWO_SIDED = range(2)
 
-PREC = {"fp64": HOTRG_FP64, "fp32": HOTRG_FP32, "bf16x3": HOTRG_BF16X3}
+PREC = {"fp64": HOTRG_FP64, "fp32": HOTRG_FP32, "bf16x3": HOTRG_BF16X3, "auto": HOTRG_PREC_AUTO}
 TRUNC = {"plain": HOTRG_TRUNC_PLAIN, "multiplet": HOTRG_TRUNC_MULTIPLET}
 MODEL = {"ising": HOTRG_ISING, "xy": HOTRG_XY, "potts": HOTRG_POTTS, "raw": HOTRG_RAW,
          "gxy": HOTRG_GXY}
@@ -30,7 +30,7 @@ EXPORTS = [
     "hotrg_run", "hotrg_environment", "hotrg_coarse", "hotrg_ctx_enable_timing", "hotrg_ctx_timings",
     "hotrg_ctx_set_workers", "hotrg_submit", "hotrg_poll", "hotrg_wait", "hotrg_cancel",
     "hotrg_footprint", "hotrg_run_batch", "hotrg_ctx_sched_stats", "hotrg_thermo",
-    "hotrg_release",
+    "hotrg_release", "hotrg_plan",
 ]
 
 PHASES = ["env", "eigh", "proj", "c1", "c2", "c3", "norm"]
@@ -51,7 +51,7 @@ class ModelParams(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("d_cut", c_int), ("n_steps", c_int), ("prec", c_int), ("trunc", c_int),
                 ("degen_tol", c_double), ("spec_len", c_int), ("eig", c_int),
-                ("isometry", c_int)]
+                ("isometry", c_int), ("tol", c_double)]
 
 
 class StepInfo(ctypes.Structure):
@@ -71,7 +71,8 @@ class PhaseTime(ctypes.Structure):
 class Result(ctypes.Structure):
     _fields_ = [("lnz_per_site", c_double), ("n_steps", c_int), ("steps", POINTER(StepInfo)),
                 ("spectra", POINTER(c_double)), ("seconds", c_double), ("t_submit", c_double),
-                ("t_start", c_double), ("t_end", c_double), ("prec_used", c_int)]
+                ("t_start", c_double), ("t_end", c_double), ("prec_used", c_int),
+                ("err_bound", c_double)]
 
 
 _lib = None
@@ -111,6 +112,8 @@ def lib():
     L.hotrg_cancel.argtypes = [vp, ctypes.c_uint64]
     L.hotrg_release.argtypes = [vp, ctypes.c_uint64]
     L.hotrg_footprint.argtypes = [POINTER(ModelParams), POINTER(Opts), POINTER(c_size_t)]
+    L.hotrg_plan.argtypes = [POINTER(ModelParams), POINTER(Opts), POINTER(c_int), POINTER(c_int),
+                             POINTER(c_double)]
     L.hotrg_run_batch.argtypes = [vp, c_int, POINTER(ModelParams), POINTER(Opts), POINTER(Result),
                                   POINTER(c_int)]
     L.hotrg_ctx_sched_stats.argtypes = [vp, POINTER(ctypes.c_uint64), POINTER(ctypes.c_uint64),
@@ -151,8 +154,9 @@ EIG = {"auto": 0, "dense": 1}
 
 
 def make_opts(d_cut, n_steps=0, prec="fp64", trunc="plain", degen_tol=1e-10, spec_len=0,
-              eig="auto", isometry="one"):
+              eig="auto", isometry="one", tol=0.0):
     o = Opts()
+    o.tol = float(tol)
     o.eig = EIG[eig] if isinstance(eig, str) else int(eig)
     o.isometry = ISOMETRY[isometry] if isinstance(isometry, str) else int(isometry)
     o.d_cut, o.n_steps = int(d_cut), int(n_steps)
@@ -224,7 +228,8 @@ def hotrg_run(ctx, params, opts):
     _check(lib().hotrg_run(ctx.ptr, byref(params), byref(opts), byref(r)))
     return {"lnz_per_site": r.lnz_per_site, "n_steps": r.n_steps,
             "steps": [infos[i].as_dict() for i in range(K)],
-            "spectra": spec[:K, :opts.spec_len], "seconds": r.seconds, "prec_used": r.prec_used}
+            "spectra": spec[:K, :opts.spec_len], "seconds": r.seconds, "prec_used": r.prec_used,
+            "err_bound": r.err_bound}
 
 
 class State:
@@ -297,7 +302,14 @@ def _result_dict(r, infos, spec, K, spec_len):
             "steps": [infos[i].as_dict() for i in range(K)] if infos is not None else [],
             "spectra": spec[:K, :spec_len] if spec is not None else None,
             "seconds": r.seconds, "t_submit": r.t_submit, "t_start": r.t_start, "t_end": r.t_end,
-            "prec_used": r.prec_used}
+            "prec_used": r.prec_used, "err_bound": r.err_bound}
+
+
+def hotrg_plan(params, opts):
+    """The precision schedule of a run: dict(prec, first_reduced, err_bound)."""
+    p, k0, e = c_int(), c_int(), c_double()
+    _check(lib().hotrg_plan(byref(params), byref(opts), byref(p), byref(k0), byref(e)))
+    return {"prec": p.value, "first_reduced": k0.value, "err_bound": e.value}
 
 
 def hotrg_footprint(params, opts):

@@ -24,6 +24,7 @@
 
 #include "../../include/hotrg.h"
 #include "internal.h"
+#include "precision.h"
 
 namespace hotrg {
 std::vector<double> ising_tensor(double beta, double J);
@@ -88,6 +89,10 @@ struct hotrg_ctx {
   void* sched = nullptr;
   int n_workers = 16;
   std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+  // test hook (environment HOTRG_TEST_EIG_FAIL_STEP, read at creation): the
+  // eigensolve of this step number reports failure, as a non-zero rocSOLVER
+  // info would; 0: off
+  int test_fail_step = 0;
   // per-phase timing
   bool timing = false;
   struct Mark {
@@ -110,13 +115,18 @@ struct hotrg_state {
   int ops_prec = HOTRG_FP64;
   Buf Tn, Xt, Tp;      // FP64 operands of the next step (normalised)
   Buf RO[4][2];        // reduced-precision operands OT, OX, OC1, OC2 ([.][0] hi/float, [.][1] lo)
-  Buf acc;             // device double: ln n_0 + sum_k 2^-k ln n_k
+  Buf acc;             // device: double ln n_0 + sum_k 2^-k ln n_k, then an int
+                       // sticky flag set when any step's eigensolve failed
   Buf recs;            // device: kRec doubles per step
   Buf spec;            // device spectra, spec_cap doubles per step
   int rec_cap = 0, spec_len = 0;
   // sweeps the last iterative eigensolve of each step parity needed, and its n
   // ([parity + 2 * side])
   int eig_sweeps[4] = {0, 0, 0, 0}, eig_n[4] = {0, 0, 0, 0};
+  // precision schedule: first step allowed in reduced precision, and the
+  // a-priori error bound of the steps run reduced so far
+  int first_reduced = 1;
+  double err_bound = 0.0;
 };
 
 namespace {
@@ -217,9 +227,26 @@ void check_opts(const hotrg_opts* o) {
     fail(HOTRG_ERR_INVALID, "eig must be HOTRG_EIG_AUTO or HOTRG_EIG_DENSE");
   if (o->isometry != HOTRG_ISO_ONE_SIDED && o->isometry != HOTRG_ISO_TWO_SIDED)
     fail(HOTRG_ERR_INVALID, "isometry must be HOTRG_ISO_ONE_SIDED or HOTRG_ISO_TWO_SIDED");
+  if (!(o->tol >= 0.0) || !std::isfinite(o->tol)) fail(HOTRG_ERR_INVALID, "tol must be >= 0");
+  if (o->prec == HOTRG_PREC_AUTO) {
+    if (!(o->tol > 0.0)) fail(HOTRG_ERR_INVALID, "HOTRG_PREC_AUTO needs tol > 0");
+    return;  // resolved by the caller (resolve_prec)
+  }
   check_prec(o->prec);
   if (o->isometry == HOTRG_ISO_TWO_SIDED && o->prec != HOTRG_FP64)
     fail(HOTRG_ERR_INVALID, "two-sided isometry needs FP64 contractions");
+}
+
+// Options with HOTRG_PREC_AUTO resolved for a run from dims (dx, dy): the
+// cheapest precision whose a-priori bound meets tol (FP64 with the two-sided
+// isometry, which has no reduced-precision path).
+hotrg_opts resolve_prec(const hotrg_opts* o, int dx, int dy) {
+  hotrg_opts r = *o;
+  if (r.prec == HOTRG_PREC_AUTO)
+    r.prec = r.isometry == HOTRG_ISO_TWO_SIDED
+                 ? HOTRG_FP64
+                 : plan_auto(r.tol, dx, dy, r.d_cut, r.n_steps).prec;
+  return r;
 }
 
 // Largest intermediate of a step with dims (dx, dy) and D' = dn, in elements.
@@ -263,6 +290,52 @@ void environment_f64(hotrg_ctx* c, const double* Tn, const double* Xt, int dx, i
            (int)n, (int)n, (int)K2, nullptr, c->stream, GEMM_TAG_ENV);
 }
 
+}  // namespace
+
+namespace hotrg {
+
+// C1, C2, C3 in FP64 on caller-provided buffers: X1 and X2 hold
+// dn*dx*dy*dx*dy doubles each, Tt receives T~[i,j,k,l] (dims dn,dy,dn,dy),
+// and *maxbits (cleared here by a kernel) max|T~|.  `tag_flags` is or-ed
+// into every GEMM tag (GEMM_NO_TUNE: fixed tile rule, no measurement, and no
+// per-phase timing events: the allocation-free entry point's path).
+void coarse_f64_into(hotrg_ctx* c, const double* Tn, const double* Tp, const double* U1,
+                     const double* U3, int dx, int dy, int dn, double* X1, double* X2, double* Tt,
+                     unsigned long long* maxbits, int tag_flags) {
+  const bool marks = tag_flags == 0;
+  const long long Q = (long long)dx * dy;
+  // C1: rows (i,a), cols (j,d,c) = j*(dx*dy) + (d*dy + c); K = b.
+  //     X1[(i,j,d),(a,c)] at ((i*dy + j)*dx + d)*Q + a*dy + c
+  //     rows (i,a): i -> dy*dx*Q, a -> dy; cols (j,d,c): j -> dx*Q, d -> Q, c -> 1
+  OutMap o1 = omap2(dx, (long long)dy * dx * Q, dy, 1, 0, 0);
+  o1.c1 = dx; o1.c2 = dy; o1.t0 = (long long)dx * Q; o1.t1 = Q; o1.t2 = 1;
+  if (marks) mark(c, HOTRG_PHASE_C1);
+  gemm_f64(U1, dx, Tn, (long long)dy * dx * dy, B_NCONTIG, X1, o1, dn * dx, dy * dx * dy, dx,
+           nullptr, c->stream, GEMM_TAG_OTHER | tag_flags);
+  // C2: rows (i,j,d) = (ij)*dx + d, cols (l,e) = l*dx + e; K = (a,c).
+  //     X2[(i,j,l),(d,e)] at ((ij)*dy + l)*dx*dx + d*dx + e
+  const long long n = (long long)dx * dx;
+  //     rows (ij,d): ij -> dy*n, d -> dx; cols (l,e): l -> n, e -> 1
+  const OutMap o2 = omap2(dx, (long long)dy * n, dx, dx, n, 1);
+  if (marks) mark(c, HOTRG_PHASE_C2);
+  gemm_f64(X1, Q, Tp, Q, B_NCONTIG, X2, o2, dn * dy * dx, (int)Q, (int)Q, nullptr, c->stream,
+           GEMM_TAG_C2 | tag_flags);
+  // C3: rows (i,j,l) = (ij)*dy + l, cols k; K = (d,e).
+  //     T~[i,j,k,l] at ((ij)*dn + k)*dy + l
+  if (marks) mark(c, HOTRG_PHASE_C3);
+  launch_store((double*)maxbits, 0.0, c->stream);  // a kernel, not a memset
+  //     rows (ij,l): ij -> dn*dy, l -> 1; cols k -> dy
+  const OutMap o3 = omap2(dy, (long long)dn * dy, 1, 1, dy, 0);
+  gemm_f64(X2, n, U3, dn, B_NCONTIG, Tt, o3, dn * dy * dy, dn, (int)n, maxbits, c->stream,
+           GEMM_TAG_OTHER | tag_flags);
+}
+
+hipStream_t ctx_stream(const hotrg_ctx* c) { return c->stream; }
+
+}  // namespace hotrg
+
+namespace {
+
 // C1, C2, C3 in FP64: T~[i,j,k,l] (dims dn,dy,dn,dy) into c->Tt, max into scal.
 void coarse_f64(hotrg_ctx* c, const double* Tn, const double* Tp, const double* U1,
                 const double* U3, int dx, int dy, int dn, unsigned long long* maxbits) {
@@ -270,31 +343,8 @@ void coarse_f64(hotrg_ctx* c, const double* Tn, const double* Tp, const double* 
   ensure(c, c->X1, (size_t)X * 8);
   ensure(c, c->X2, (size_t)X * 8);
   ensure(c, c->Tt, (size_t)dn * dy * dn * dy * 8);
-  const long long Q = (long long)dx * dy;
-  // C1: rows (i,a), cols (j,d,c) = j*(dx*dy) + (d*dy + c); K = b.
-  //     X1[(i,j,d),(a,c)] at ((i*dy + j)*dx + d)*Q + a*dy + c
-  //     rows (i,a): i -> dy*dx*Q, a -> dy; cols (j,d,c): j -> dx*Q, d -> Q, c -> 1
-  OutMap o1 = omap2(dx, (long long)dy * dx * Q, dy, 1, 0, 0);
-  o1.c1 = dx; o1.c2 = dy; o1.t0 = (long long)dx * Q; o1.t1 = Q; o1.t2 = 1;
-  mark(c, HOTRG_PHASE_C1);
-  gemm_f64(U1, dx, Tn, (long long)dy * dx * dy, B_NCONTIG, (double*)c->X1.p, o1, dn * dx,
-           dy * dx * dy, dx, nullptr, c->stream);
-  // C2: rows (i,j,d) = (ij)*dx + d, cols (l,e) = l*dx + e; K = (a,c).
-  //     X2[(i,j,l),(d,e)] at ((ij)*dy + l)*dx*dx + d*dx + e
-  const long long n = (long long)dx * dx;
-  //     rows (ij,d): ij -> dy*n, d -> dx; cols (l,e): l -> n, e -> 1
-  const OutMap o2 = omap2(dx, (long long)dy * n, dx, dx, n, 1);
-  mark(c, HOTRG_PHASE_C2);
-  gemm_f64((const double*)c->X1.p, Q, Tp, Q, B_NCONTIG, (double*)c->X2.p, o2, dn * dy * dx,
-           (int)Q, (int)Q, nullptr, c->stream, GEMM_TAG_C2);
-  // C3: rows (i,j,l) = (ij)*dy + l, cols k; K = (d,e).
-  //     T~[i,j,k,l] at ((ij)*dn + k)*dy + l
-  mark(c, HOTRG_PHASE_C3);
-  HIPCHK(hipMemsetAsync(maxbits, 0, 8, c->stream));
-  //     rows (ij,l): ij -> dn*dy, l -> 1; cols k -> dy
-  const OutMap o3 = omap2(dy, (long long)dn * dy, 1, 1, dy, 0);
-  gemm_f64((const double*)c->X2.p, n, U3, dn, B_NCONTIG, (double*)c->Tt.p, o3, dn * dy * dy, dn,
-           (int)n, maxbits, c->stream);
+  coarse_f64_into(c, Tn, Tp, U1, U3, dx, dy, dn, (double*)c->X1.p, (double*)c->X2.p,
+                  (double*)c->Tt.p, maxbits, 0);
 }
 
 void prepare_operands(hotrg_ctx* c, hotrg_state* st, int prec, const void* src, bool src_f32,
@@ -309,7 +359,7 @@ hotrg_state* new_state(hotrg_ctx* c, const std::vector<double>& T0, int dx, int 
     st->dx = dx;
     st->dy = dy;
     const size_t ne = T0.size();
-    ensure(c, st->acc, 8);
+    ensure(c, st->acc, 16);
     ensure(c, c->scal, 64);
     // upload through the Tt workspace as FP64
     ensure(c, c->Tt, ne * 8);
@@ -328,11 +378,12 @@ hotrg_state* new_state(hotrg_ctx* c, const std::vector<double>& T0, int dx, int 
   return st;
 }
 
-// Precision of a step's contractions: reduced (FP32 or split BF16) only in
-// the steady state, where both legs already have the kept dimension; the
-// few warm-up steps before it stay FP64.
-int step_precision(const hotrg_state* st, int dx, int dy, int d_cut) {
-  return (st->prec != HOTRG_FP64 && dx >= d_cut && dy >= d_cut) ? st->prec : HOTRG_FP64;
+// Precision of step k's contractions: reduced (FP32 or split BF16) only in
+// the steady state, where both legs already have the kept dimension, and
+// from the state's first_reduced step on (precision.h); the warm-up steps
+// and the heavily weighted early steps a tolerance asks for stay FP64.
+int step_precision(const hotrg_state* st, int k, int dx, int dy, int d_cut) {
+  return step_is_reduced(st->prec, k, dx, dy, d_cut, st->first_reduced) ? st->prec : HOTRG_FP64;
 }
 
 int rp_mode(int prec) { return prec == HOTRG_FP32 ? RP_F32 : RP_BF16X3; }
@@ -447,7 +498,7 @@ void coarse_rp(hotrg_ctx* c, hotrg_state* st, int mode, int dx, int dy, int dn,
                      nullptr, c->stream, GEMM_TAG_C2);
   // C3: rows (ij,l): ij -> dn*dy, l -> 1; cols k -> dy
   mark(c, HOTRG_PHASE_C3);
-  HIPCHK(hipMemsetAsync(maxbits, 0, 8, c->stream));
+  launch_store((double*)maxbits, 0.0, c->stream);
   const OutMap o3 = omap2(dy, (long long)dn * dy, 1, 1, dy, 0);
   ok = ok && gemm_rp(mode, op(c->RX2), ldn, op(c->RU3), ldn, RP_OUT_F32, c->Tt.p, nullptr, o3,
                      (int)x2rows, dn, (int)ldn, maxbits, c->stream, GEMM_TAG_OTHER);
@@ -482,8 +533,9 @@ void do_step(hotrg_ctx* c, hotrg_state* st, const hotrg_opts* o) {
   int* info = (int*)((char*)c->scal.p + 8);
   int* kept = (int*)((char*)c->scal.p + 16);
   unsigned long long* one = (unsigned long long*)((char*)c->scal.p + 56);
+  int* st_fail = (int*)((char*)st->acc.p + 8);
 
-  const int sp = step_precision(st, dx, dy, o->d_cut);
+  const int sp = step_precision(st, k, dx, dy, o->d_cut);
   if (sp != st->ops_prec) {
     // operands were prepared for another precision (d_cut changed): rebuild
     const unsigned long long one_bits = 0x3ff0000000000000ULL;
@@ -551,11 +603,14 @@ void do_step(hotrg_ctx* c, hotrg_state* st, const hotrg_opts* o) {
                                          (double*)Mb.p, n, (double*)Wb.p, (double*)c->E.p, inf);
     if (rs != rocblas_status_success)
       fail(HOTRG_ERR_DEVICE, "rocsolver_dsyevd failed with status " + std::to_string((int)rs));
+    // a non-converged solve marks the state: later solves overwrite `inf`
+    launch_fold_info(inf, st_fail, 0, c->stream);
     *cols_out = n;
     return (const double*)Mb.p;
   };
   int cols = n;
   const double* evec = solve(c->M, c->W, c->Xr, 0, info, &cols);
+  if (k == c->test_fail_step) launch_fold_info(info, st_fail, 1, c->stream);
   mark(c, HOTRG_PHASE_PROJ);
   launch_spectrum((const double*)c->W.p, cols, n, dn, o->trunc, o->degen_tol, st->spec_len,
                   trace, spec, rec, kept, c->stream);
@@ -585,12 +640,13 @@ void do_step(hotrg_ctx* c, hotrg_state* st, const hotrg_opts* o) {
     launch_spectrum((const double*)c->W2.p, cols2, n, dn, o->trunc, o->degen_tol, st->spec_len,
                     trace2, spec2, rec2, kept2, c->stream);
     double errs[2] = {0.0, 0.0};
-    int inf2 = 0;
+    int sticky = 0;
     HIPCHK(hipMemcpyAsync(&errs[0], rec + 1, 8, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipMemcpyAsync(&errs[1], rec2 + 1, 8, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipMemcpyAsync(&inf2, info2, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(&sticky, st_fail, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
-    if (inf2 != 0) fail(HOTRG_ERR_NUMERIC, "eigensolver did not converge (right environment)");
+    // both solves of this step (and every earlier one) are folded into the flag
+    if (sticky != 0) fail(HOTRG_ERR_NUMERIC, "eigensolver did not converge");
     if (errs[1] < errs[0] - kSideMargin) {
       HIPCHK(hipMemcpyAsync(rec, rec2, 5 * 8, hipMemcpyDeviceToDevice, c->stream));
       HIPCHK(hipMemcpyAsync(kept, kept2, sizeof(int), hipMemcpyDeviceToDevice, c->stream));
@@ -631,10 +687,11 @@ void do_step(hotrg_ctx* c, hotrg_state* st, const hotrg_opts* o) {
   const bool tt_f32 = sp != HOTRG_FP64;
   launch_norm(mb, c->Tt.p, tt_f32, dn, dy, std::ldexp(1.0, -k), (double*)st->acc.p, rec, c->stream);
   const int ndx = dy, ndy = dn;
-  const int nsp = step_precision(st, ndx, ndy, o->d_cut);
+  const int nsp = step_precision(st, k + 1, ndx, ndy, o->d_cut);
   prepare_operands(c, st, nsp, c->Tt.p, tt_f32, true, ndx, ndy, mb);
   mark(c, -1);
   HIPCHK(hipGetLastError());
+  if (sp != HOTRG_FP64) st->err_bound += kErrPerStep[sp] * std::ldexp(1.0, -k);
   st->dx = ndx;
   st->dy = ndy;
   st->k = k;
@@ -663,11 +720,13 @@ void fetch_info(hotrg_ctx* c, hotrg_state* st, int first, int count, const int* 
   (void)dims_dx;
 }
 
-void check_info(hotrg_ctx* c) {
-  int info = 0;
-  HIPCHK(hipMemcpyAsync(&info, (char*)c->scal.p + 8, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+// The state's sticky flag: set if the eigensolve of any step so far failed.
+void check_info(hotrg_ctx* c, const hotrg_state* st) {
+  int flag = 0;
+  HIPCHK(hipMemcpyAsync(&flag, (const char*)st->acc.p + 8, sizeof(int), hipMemcpyDeviceToHost,
+                        c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
-  if (info != 0) fail(HOTRG_ERR_NUMERIC, "eigensolver did not converge (info " + std::to_string(info) + ")");
+  if (flag != 0) fail(HOTRG_ERR_NUMERIC, "eigensolver did not converge in an earlier step");
 }
 
 std::vector<double> build_tensor(const hotrg_model_params* p, int* dx, int* dy) {
@@ -723,17 +782,22 @@ hotrg_status guard(F&& f) {
 
 namespace hotrg {
 
-hotrg_status run_problem(hotrg_ctx* c, const hotrg_model_params* params, const hotrg_opts* o,
+hotrg_status run_problem(hotrg_ctx* c, const hotrg_model_params* params, const hotrg_opts* o_in,
                          hotrg_result* res, const std::atomic<bool>* cancel) {
   hotrg_state* st = nullptr;
   hotrg_status s = guard([&] {
     if (!c || !res) fail(HOTRG_ERR_INVALID, "ctx/result is NULL");
-    check_opts(o);
+    check_opts(o_in);
     HIPCHK(hipSetDevice(c->device));
     auto t0 = std::chrono::steady_clock::now();
     int dx = 0, dy = 0;
     std::vector<double> T0 = build_tensor(params, &dx, &dy);
+    const hotrg_opts ro = resolve_prec(o_in, dx, dy);
+    const hotrg_opts* o = &ro;
+    check_opts(o);
+    if (cancel && cancel->load()) fail(HOTRG_ERR_CANCELLED, "cancelled");
     st = new_state(c, T0, dx, dy, o->prec);
+    st->first_reduced = first_reduced_step(o->prec, o->tol);
     std::vector<int> dxs, dys, dns;
     for (int k = 0; k < o->n_steps; ++k) {
       if (cancel && cancel->load()) fail(HOTRG_ERR_CANCELLED, "cancelled");
@@ -757,6 +821,7 @@ hotrg_status run_problem(hotrg_ctx* c, const hotrg_model_params* params, const h
     res->lnz_per_site = lnz;
     res->n_steps = o->n_steps;
     res->prec_used = o->prec;
+    res->err_bound = st->err_bound;
     res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   });
   if (st) hotrg_state_free(c, st);
@@ -780,6 +845,7 @@ double ctx_seconds(const hotrg_ctx* c) {
 int ctx_device(const hotrg_ctx* c) { return c->device; }
 size_t ctx_budget(const hotrg_ctx* c) { return c->budget; }
 int& ctx_workers(hotrg_ctx* c) { return c->n_workers; }
+int& ctx_test_fail_step(hotrg_ctx* c) { return c->test_fail_step; }
 void*& ctx_sched(hotrg_ctx* c) { return c->sched; }
 const char* last_error_text() { return g_err.c_str(); }
 void set_last_error(const char* m) { g_err = m; }
@@ -800,6 +866,7 @@ hotrg_status hotrg_ctx_create(int device, void* hip_stream, size_t hbm_budget, h
     HIPCHK(hipSetDevice(device));
     auto* c = new hotrg_ctx();
     c->device = device;
+    if (const char* e = getenv("HOTRG_TEST_EIG_FAIL_STEP")) c->test_fail_step = atoi(e);
     c->budget = hbm_budget;
     if (hip_stream) {
       c->stream = (hipStream_t)hip_stream;
@@ -865,11 +932,14 @@ hotrg_status hotrg_step(hotrg_ctx* c, hotrg_state* st, const hotrg_opts* o, hotr
     check_opts(o);
     if (o->isometry == HOTRG_ISO_TWO_SIDED && st->prec != HOTRG_FP64)
       fail(HOTRG_ERR_INVALID, "two-sided isometry needs FP64 contractions");
+    if (o->prec == HOTRG_PREC_AUTO)
+      fail(HOTRG_ERR_INVALID, "HOTRG_PREC_AUTO applies to whole runs only");
     HIPCHK(hipSetDevice(c->device));
     const int dx = st->dx, dy = st->dy;
+    st->first_reduced = first_reduced_step(st->prec, o->tol);
     do_step(c, st, o);
     if (info || spectrum) {
-      check_info(c);
+      check_info(c, st);
       hotrg_step_info tmp;
       double* sp = nullptr;
       std::vector<double> spv;
@@ -899,7 +969,7 @@ hotrg_status hotrg_finish(hotrg_ctx* c, hotrg_state* st, double* lnz) {
     double v = 0;
     HIPCHK(hipMemcpyAsync(&v, outp, 8, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
-    if (st->k > 0) check_info(c);
+    if (st->k > 0) check_info(c, st);
     if (!std::isfinite(v)) fail(HOTRG_ERR_NUMERIC, "non-finite ln Z (norm or trace <= 0)");
     *lnz = v;
   });
@@ -948,6 +1018,21 @@ void hotrg_state_free(hotrg_ctx* c, hotrg_state* st) {
 hotrg_status hotrg_run(hotrg_ctx* c, const hotrg_model_params* params, const hotrg_opts* o,
                        hotrg_result* res) {
   return hotrg::run_problem(c, params, o, res, nullptr);
+}
+
+hotrg_status hotrg_plan(const hotrg_model_params* params, const hotrg_opts* o, int* prec,
+                        int* first_reduced, double* err_bound) {
+  return guard([&] {
+    check_opts(o);
+    int dx = 0, dy = 0;
+    (void)build_tensor(params, &dx, &dy);
+    const hotrg_opts r = resolve_prec(o, dx, dy);
+    check_opts(&r);
+    const PrecPlan pl = plan_precision(r.prec, r.tol, dx, dy, r.d_cut, r.n_steps);
+    if (prec) *prec = pl.err_bound > 0.0 ? r.prec : HOTRG_FP64;
+    if (first_reduced) *first_reduced = pl.first_reduced;
+    if (err_bound) *err_bound = pl.err_bound;
+  });
 }
 
 hotrg_status hotrg_ctx_enable_timing(hotrg_ctx* c, int on) {

@@ -460,6 +460,8 @@ void gemm_f64(const double* A, long long lda, const double* B, long long ldb, in
               double* C, const OutMap& om, int M, int N, int K, unsigned long long* maxbits,
               hipStream_t s, int tag) {
   if (M <= 0 || N <= 0) return;
+  const bool no_tune = (tag & GEMM_NO_TUNE) != 0;
+  tag &= ~GEMM_NO_TUNE;
   static const int forced = [] {
     const char* e = std::getenv("HOTRG_GEMM_VARIANT");
     return e ? std::atoi(e) : -1;
@@ -499,7 +501,7 @@ void gemm_f64(const double* A, long long lda, const double* B, long long ldb, in
         return true;
     }
   };
-  if (forced < 0 && autotune_on() && (long long)M * N >= (1LL << 20)) {
+  if (!no_tune && forced < 0 && autotune_on() && (long long)M * N >= (1LL << 20)) {
     bool tuned = false;
     const int c = tune(make_key(0, lda, ldb, blayout, om, M, N, K, maxbits != nullptr, tag),
                        C_COUNT, cand, s, &tuned);

@@ -38,8 +38,9 @@ inline OutMap out_rowmajor(long long ld) { return omap2(1, ld, 0, 1, 1, 0); }
 
 enum BLayout { B_NCONTIG = 0, B_KCONTIG = 1 };
 
-// Call-site tags: large GEMMs get a kernel symbol per tag.
-enum GemmTag { GEMM_TAG_OTHER = 0, GEMM_TAG_ENV = 1, GEMM_TAG_C2 = 2 };
+// Call-site tags: large GEMMs get a kernel symbol per tag.  GEMM_NO_TUNE, or-ed
+// into a tag, keeps the fixed tile rule (no timed candidate runs, no host wait).
+enum GemmTag { GEMM_TAG_OTHER = 0, GEMM_TAG_ENV = 1, GEMM_TAG_C2 = 2, GEMM_NO_TUNE = 0x100 };
 
 // C[map(m,n)] = sum_k A[m*lda + k] * B(k, n), FP64 MFMA.
 // B(k, n) = B[k*ldb + n] for B_NCONTIG, B[n*ldb + k] for B_KCONTIG.
@@ -114,6 +115,8 @@ void launch_layout_u_rp(const double* Ucan, int dx, int dn, int mode, void* u1hi
 // ---- small kernels (kernels.hip) ----
 void launch_maxabs(const void* x, long long n, bool is_f32, unsigned long long* maxbits, hipStream_t s);
 void launch_init_acc(const unsigned long long* maxbits, double* acc, hipStream_t s);
+// Sticky eigensolver failure: *flag = 1 if *info != 0 or force.
+void launch_fold_info(const int* info, int* flag, int force, hipStream_t s);
 // Operands of the next step from the coarse tensor `src` (f64 or f32),
 // optionally with legs transposed (l,u,r,d) -> (u,l,d,r), scaled by
 // 1/max (read from maxbits): Tn natural (dx,dy,dx,dy); Xt [(l,d),(u,r)];
@@ -146,6 +149,12 @@ void launch_f64_to_f32(const double* x, float* y, long long n, hipStream_t s);
 void launch_f32_to_f64(const float* x, double* y, long long n, hipStream_t s);
 
 // ---- engine hooks used by the scheduler (sched.cpp) ----
+// C1 -> C2 -> C3 in FP64 on caller buffers (X1, X2: dn*dx*dy*dx*dy doubles;
+// Tt: dn*dy*dn*dy); *maxbits is cleared by a kernel and receives max|Tt|.
+void coarse_f64_into(hotrg_ctx* c, const double* Tn, const double* Tp, const double* U1,
+                     const double* U3, int dx, int dy, int dn, double* X1, double* X2, double* Tt,
+                     unsigned long long* maxbits, int tag_flags);
+hipStream_t ctx_stream(const hotrg_ctx* c);
 // hotrg_run with a cancellation flag checked between steps.
 hotrg_status run_problem(hotrg_ctx* c, const hotrg_model_params* params, const hotrg_opts* o,
                          hotrg_result* res, const std::atomic<bool>* cancel);
@@ -154,6 +163,7 @@ double ctx_seconds(const hotrg_ctx* c);
 int ctx_device(const hotrg_ctx* c);
 size_t ctx_budget(const hotrg_ctx* c);
 int& ctx_workers(hotrg_ctx* c);
+int& ctx_test_fail_step(hotrg_ctx* c);  // failure-injection hook, 0: off
 void*& ctx_sched(hotrg_ctx* c);
 void sched_shutdown(hotrg_ctx* c);
 const char* last_error_text();

@@ -40,8 +40,22 @@ void launch_maxabs(const void* x, long long n, bool is_f32, unsigned long long* 
                      0, s, x, n, is_f32, maxbits);
 }
 
+// acc[0] = ln n_0; the state's sticky failure flag (an int in acc[1]) is cleared
 __global__ void k_init_acc(const unsigned long long* maxbits, double* acc) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) acc[0] = log(__longlong_as_double((long long)*maxbits));
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    acc[0] = log(__longlong_as_double((long long)*maxbits));
+    *(int*)(acc + 1) = 0;
+  }
+}
+
+// *flag = 1 when *info != 0 (or `force`): a failed eigensolve of any step stays
+// visible until the state is finished
+__global__ void k_fold_info(const int* info, int* flag, int force) {
+  if (threadIdx.x == 0 && blockIdx.x == 0 && (force || *info != 0)) *flag = 1;
+}
+
+void launch_fold_info(const int* info, int* flag, int force, hipStream_t s) {
+  hipLaunchKernelGGL(k_fold_info, dim3(1), dim3(64), 0, s, info, flag, force);
 }
 
 void launch_init_acc(const unsigned long long* maxbits, double* acc, hipStream_t s) {

@@ -29,6 +29,7 @@
 
 #include "admit.h"
 #include "internal.h"
+#include "precision.h"
 
 namespace hotrg {
 size_t topk_workspace_doubles(int n, int p);
@@ -104,9 +105,23 @@ bool initial_dims(const hotrg_model_params* p, int* dx, int* dy) {
   }
 }
 
-size_t footprint_of(const hotrg_model_params* p, const hotrg_opts* o) {
+// HOTRG_PREC_AUTO resolved as run_problem resolves it
+hotrg_opts resolved(const hotrg_model_params* p, const hotrg_opts* o) {
+  hotrg_opts r = *o;
+  int dx = 0, dy = 0;
+  if (r.prec == HOTRG_PREC_AUTO && initial_dims(p, &dx, &dy))
+    r.prec = r.isometry == HOTRG_ISO_TWO_SIDED
+                 ? HOTRG_FP64
+                 : plan_auto(r.tol, dx, dy, r.d_cut, r.n_steps).prec;
+  return r;
+}
+
+size_t footprint_of(const hotrg_model_params* p, const hotrg_opts* o_in) {
   int dx = 0, dy = 0;
   if (!initial_dims(p, &dx, &dy)) return 0;
+  const hotrg_opts ro = resolved(p, o_in);
+  const hotrg_opts* o = &ro;
+  const int k0 = first_reduced_step(o->prec, o->tol);
   std::map<std::string, size_t> peak;
   auto need = [&](const char* name, double bytes) {
     size_t b = (size_t)bytes;
@@ -118,7 +133,7 @@ size_t footprint_of(const hotrg_model_params* p, const hotrg_opts* o) {
     const double n = (double)dx * dx, P = (double)dx * dy;
     const int dn = (int)std::min<long long>(o->d_cut, (long long)dx * dx);
     const double X = (double)dn * dx * dx * dy * dy;
-    const bool red = o->prec != HOTRG_FP64 && dx >= o->d_cut && dy >= o->d_cut;
+    const bool red = step_is_reduced(o->prec, k + 1, dx, dy, o->d_cut, k0);
     need("M", n * n * 8);
     need("WE", 2 * n * 8);
     need("U", 3 * n * dn * 8);
@@ -221,7 +236,9 @@ void worker_loop(Server* S, int w) {
       S->reserved -= r->footprint + hold;
       hold = held;
       S->reserved += hold;
-      if (retry && f64 <= S->budget) {
+      // a cancel that arrived while the request ran found it Q_RUNNING and did
+      // not take it off the queue: it must not be queued again
+      if (retry && f64 <= S->budget && !r->cancel.load()) {
         // reduced-precision noise drove the run off: queue it once more in FP64
         r->opts = o64;
         r->footprint = f64;
@@ -259,6 +276,7 @@ Server* server_of(hotrg_ctx* c, bool create) {
   for (int i = 0; i < nw; ++i) {
     hotrg_ctx* w = nullptr;
     if (hotrg_ctx_create(ctx_device(c), nullptr, 0, &w) != HOTRG_OK) break;
+    ctx_test_fail_step(w) = ctx_test_fail_step(c);
     S->workers.push_back(w);
   }
   if (S->workers.empty()) {
@@ -345,9 +363,14 @@ hotrg_status hotrg_submit(hotrg_ctx* ctx, const hotrg_model_params* params, cons
     r->raw.assign(params->raw, params->raw + ne);
     r->params.raw = r->raw.data();
   }
-  r->opts = *opts;
+  if (opts->prec == HOTRG_PREC_AUTO && !(opts->tol > 0.0)) {
+    set_last_error("HOTRG_PREC_AUTO needs tol > 0");
+    return HOTRG_ERR_INVALID;
+  }
+  // the precision is chosen at admission: the cheapest that meets tol
+  r->opts = resolved(params, opts);
   r->out = result;
-  r->footprint = footprint_of(params, opts);
+  r->footprint = footprint_of(params, &r->opts);
   if (r->footprint == 0) {
     set_last_error("unknown model or bad dimensions");
     return HOTRG_ERR_INVALID;

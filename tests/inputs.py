@@ -25,3 +25,25 @@ def poisson_arrivals(n, rate, seed):
     """Arrival times (seconds) of n requests of a Poisson process."""
     rng = np.random.default_rng(seed)
     return np.cumsum(rng.exponential(1.0 / rate, size=n))
+
+
+def serving_stream(n, seed):
+    """A seeded mix of small FP64 requests for the serving parity test:
+    tuples (model, beta, n_max, q, d_cut, n_steps).  Ising at T ~ U[1.5, 3.5],
+    XY at beta ~ U[0.6, 1.6] with n_max in {2, 3}, 3-state Potts at
+    beta ~ U[0.8, 1.2]; D_cut in {8, 12, 16, 24} (at most 16 for XY / Potts);
+    10 to 24 directional steps."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        u = rng.random()
+        if u < 0.45:
+            out.append(("ising", 1.0 / rng.uniform(1.5, 3.5), 0, 2,
+                        int(rng.choice([8, 12, 16, 24])), int(rng.integers(10, 25))))
+        elif u < 0.85:
+            out.append(("xy", rng.uniform(0.6, 1.6), int(rng.integers(2, 4)), 2,
+                        int(rng.choice([8, 12, 16])), int(rng.integers(10, 25))))
+        else:
+            out.append(("potts", rng.uniform(0.8, 1.2), 0, 3,
+                        int(rng.choice([8, 12, 16])), int(rng.integers(10, 25))))
+    return out

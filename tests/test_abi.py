@@ -45,7 +45,7 @@ def test_struct_layouts_match_header():
     from paper_2306_00358_amd import _lib
 
     assert ctypes.sizeof(_lib.StepInfo) == 4 * 4 + 4 * 8 + 8  # side, padded
-    assert ctypes.sizeof(_lib.Opts) == 4 * 4 + 8 + 3 * 4 + 4  # 4 ints, double, 3 ints, pad
+    assert ctypes.sizeof(_lib.Opts) == 4 * 4 + 8 + 3 * 4 + 4 + 8  # 4 ints, double, 3 ints, pad, tol
     assert [f for f, _ in _lib.ModelParams._fields_] == [
         "model", "beta", "J", "n_max", "q", "raw", "raw_dx", "raw_dy", "delta"]
 

@@ -324,3 +324,45 @@ def test_gxy_untruncated_one_step_equals_charge_sum_and_quadrature():
     w = np.exp(beta * delta * np.cos(th) + beta * (1 - delta) * np.cos(2 * th))
     Z = np.mean(w * w) * np.exp(2 * beta)  # two vertical bonds, two self-bonds at angle 0
     assert c.sum() ** 2 * (c * c).sum() == pytest.approx(Z, rel=1e-13)
+
+
+# ------------------------------------------------------ truncation error --
+# epsilon = 1 - sum_{m <= kept} s_m / sum_m s_m is the share of the
+# environment's trace that the projector does not keep (M is PSD, so its
+# singular values are its eigenvalues and sum to trace(M)).  Pinned without
+# the function's own formula: a known spectrum in closed form, and the trace
+# of M projected onto the kept columns, 1 - trace(U U^T M) / trace(M).
+
+
+def _pin_truncation_error():
+    worst = 0.0
+    # closed form: M = Q diag(8, 4, 2, 1, 1/2) Q^T, Q a random rotation
+    lam = np.array([8.0, 4.0, 2.0, 1.0, 0.5])
+    Q, _ = np.linalg.qr(np.random.default_rng(3).standard_normal((5, 5)))
+    M = Q @ np.diag(lam) @ Q.T
+    for d_cut, want in [(1, 1.0 - 8.0 / 15.5), (2, 1.0 - 12.0 / 15.5), (3, 1.0 - 14.0 / 15.5),
+                        (4, 1.0 - 15.0 / 15.5), (5, 0.0)]:
+        _, s, _, kept = hotrg.projector(M, d_cut)
+        worst = max(worst, abs(hotrg.truncation_error(s, kept) - want))
+    # projected trace of real environments (plain and multiplet cuts)
+    for T, d_cut, trunc in [(tensors.ising(0.44), 3, "plain"), (tensors.xy(1.0, 2), 7, "multiplet"),
+                            (tensors.potts(0.9, 3), 4, "plain")]:
+        M = hotrg.environment(T)
+        U, s, _, kept = hotrg.projector(M, d_cut, trunc, 1e-10)
+        direct = 1.0 - np.trace(U @ U.T @ M) / np.trace(M)
+        worst = max(worst, abs(hotrg.truncation_error(s, kept) - direct))
+    return worst
+
+
+def test_truncation_error_pinned():
+    assert _pin_truncation_error() <= 1e-13
+
+
+@pytest.mark.parametrize("wrong", [
+    lambda s, kept: float(1.0 - (s[:kept] ** 2).sum() / (s ** 2).sum()),  # squared values
+    lambda s, kept: float(1.0 - s[:kept].sum() / s[0]),                 # divided by s_1
+    lambda s, kept: float(1.0 - s[:kept + 1].sum() / s.sum()),          # one value too many
+])
+def test_planted_truncation_error_is_caught(monkeypatch, wrong):
+    monkeypatch.setattr(hotrg, "truncation_error", wrong)
+    assert _pin_truncation_error() > 1e-3
