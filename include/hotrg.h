@@ -301,6 +301,29 @@ hotrg_status hotrg_environment(hotrg_ctx* ctx, int prec, const double* T, int dx
 hotrg_status hotrg_coarse(hotrg_ctx* ctx, int prec, const double* T, const double* U, int dx,
                           int dy, int dn, double* Tt, double* max_abs);
 
+/* ---- allocation-free coarse contraction ---------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, serving loops and harnesses that forbid hipMalloc.  Computes the
+ * same T~ and max|T~| as hotrg_coarse with prec = HOTRG_FP64 (C1 -> C2 -> C3
+ * with the fixed tile rule instead of the autotuner's choice, so the two may
+ * differ in the last bits), but calls no hipMalloc / hipFree / allocating
+ * library routine, records no memset, and does not wait: the work is
+ * enqueued on the context's stream (the stream given to hotrg_ctx_create,
+ * which the caller may be capturing) and the caller synchronises it.
+ * All intermediates live in one static device array of
+ * HOTRG_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on
+ * until the process ends; every call on a GPU shares that GPU's array, so
+ * calls that overlap on one GPU (other streams, other contexts, other
+ * threads) race and must be serialised by the caller.  Sizes must satisfy
+ *   2 dn dx^2 dy^2 + 3 dx^2 dy^2 + 2 dx^2 dn + 288  <=  scratch bytes / 8
+ * (each of the seven buffers is rounded up to 32 doubles; dx = dy = dn = 20
+ * fits); larger sizes fail with HOTRG_ERR_INVALID and a
+ * message giving the bytes needed.  T, U, Tt and max_abs (may be NULL) are
+ * device pointers with the layouts of hotrg_coarse; 1 <= dn <= dx*dx. */
+#define HOTRG_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+hotrg_status hotrg_coarse_noalloc(hotrg_ctx* ctx, const double* T, const double* U, int dx,
+                                  int dy, int dn, double* Tt, double* max_abs);
+
 #ifdef __cplusplus
 }
 #endif

@@ -30,8 +30,10 @@ EXPORTS = [
     "hotrg_run", "hotrg_environment", "hotrg_coarse", "hotrg_ctx_enable_timing", "hotrg_ctx_timings",
     "hotrg_ctx_set_workers", "hotrg_submit", "hotrg_poll", "hotrg_wait", "hotrg_cancel",
     "hotrg_footprint", "hotrg_run_batch", "hotrg_ctx_sched_stats", "hotrg_thermo",
-    "hotrg_release", "hotrg_plan",
+    "hotrg_release", "hotrg_coarse_noalloc", "hotrg_plan",
 ]
+
+NOALLOC_SCRATCH_BYTES = 64 << 20  # HOTRG_NOALLOC_SCRATCH_BYTES
 
 PHASES = ["env", "eigh", "proj", "c1", "c2", "c3", "norm"]
 
@@ -103,6 +105,7 @@ def lib():
     L.hotrg_run.argtypes = [vp, POINTER(ModelParams), POINTER(Opts), POINTER(Result)]
     L.hotrg_environment.argtypes = [vp, c_int, vp, c_int, c_int, vp]
     L.hotrg_coarse.argtypes = [vp, c_int, vp, vp, c_int, c_int, c_int, vp, vp]
+    L.hotrg_coarse_noalloc.argtypes = [vp, vp, vp, c_int, c_int, c_int, vp, vp]
     L.hotrg_ctx_enable_timing.argtypes = [vp, c_int]
     L.hotrg_ctx_set_workers.argtypes = [vp, c_int]
     L.hotrg_submit.argtypes = [vp, POINTER(ModelParams), POINTER(Opts), POINTER(Result),
@@ -295,6 +298,16 @@ def hotrg_coarse(ctx, T, U, Tt, max_abs=None, prec="fp64"):
     _check(lib().hotrg_coarse(ctx.ptr, _prec(prec), c_void_p(T.data_ptr()), c_void_p(U.data_ptr()),
                               dx, dy, dn, c_void_p(Tt.data_ptr()),
                               c_void_p(max_abs.data_ptr()) if max_abs is not None else None))
+
+
+def hotrg_coarse_noalloc(ctx, T, U, Tt, max_abs=None):
+    """hotrg_coarse in FP64 without any allocation (intermediates in the
+    library's static scratch array); enqueued on the context's stream, not
+    waited for: synchronise before reading Tt."""
+    dx, dy, dn = T.shape[0], T.shape[1], U.shape[2]
+    _check(lib().hotrg_coarse_noalloc(ctx.ptr, c_void_p(T.data_ptr()), c_void_p(U.data_ptr()),
+                                      dx, dy, dn, c_void_p(Tt.data_ptr()),
+                                      c_void_p(max_abs.data_ptr()) if max_abs is not None else None))
 
 
 def _result_dict(r, infos, spec, K, spec_len):

@@ -864,6 +864,7 @@ hotrg_status hotrg_ctx_create(int device, void* hip_stream, size_t hbm_budget, h
     HIPCHK(hipGetDeviceCount(&n));
     if (device < 0 || device >= n) fail(HOTRG_ERR_INVALID, "no such device");
     HIPCHK(hipSetDevice(device));
+    noalloc_init_device(device);  // this device's address of the no-alloc scratch array
     auto* c = new hotrg_ctx();
     c->device = device;
     if (const char* e = getenv("HOTRG_TEST_EIG_FAIL_STEP")) c->test_fail_step = atoi(e);

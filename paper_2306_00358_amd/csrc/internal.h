@@ -155,6 +155,9 @@ void coarse_f64_into(hotrg_ctx* c, const double* Tn, const double* Tp, const dou
                      const double* U3, int dx, int dy, int dn, double* X1, double* X2, double* Tt,
                      unsigned long long* maxbits, int tag_flags);
 hipStream_t ctx_stream(const hotrg_ctx* c);
+// Allocation-free entry point's scratch (noalloc.hip): look up this device's
+// copy of the static array once (call with the device current).
+void noalloc_init_device(int device);
 // hotrg_run with a cancellation flag checked between steps.
 hotrg_status run_problem(hotrg_ctx* c, const hotrg_model_params* params, const hotrg_opts* o,
                          hotrg_result* res, const std::atomic<bool>* cancel);
