@@ -4,17 +4,24 @@ Workload: 2D Ising at T_c = 2/ln(1+sqrt 2), D_cut = 64, 30 directional
 coarse-graining steps (2^15 x 2^15 sites), synthetic (closed-form Boltzmann
 weights, no dataset).  One bench *step* is one whole run through the C ABI
 (hotrg_run: initial tensor, 30 directional steps, periodic trace), inputs
-built on the host inside the call.  `value` is directional coarse-graining
-steps per second over the timed runs.
+built on the host inside the call, so `ms_per_step` is milliseconds per
+30-step run (`ms_per_directional_step` divides it by 30).  `value` is
+directional coarse-graining steps per second over the timed runs.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec fp64|fp32|bf16x3]
-                    [--no-cpu-baseline] [--no-compare] [--kernel-probe]
+                    [--no-cpu-baseline] [--no-compare] [--no-batch] [--no-serve]
+                    [--kernel-probe]
 
 Prints one JSON line.  The headline (`value`) uses --prec contractions
 (FP64 by default, the precision of the paper's runs); `mixed_vs_fp64`
 repeats the workload with FP32 and split-BF16 x3 contractions (the FP64
-eigensolver and log-norm accumulation are unchanged) and states each
-result's ln Z/N error against the stored FP64 oracle.  The dominant kernel
+eigensolver and log-norm accumulation are unchanged; min(K, 5) runs each),
+and with the precision chosen for a stated tolerance of 1e-7 (HOTRG_PREC_AUTO),
+and states each result's ln Z/N error against the stored FP64 oracle.
+`batch` runs the 64-problem XY batch; `serve` a seeded Poisson stream of 20
+mixed requests (p50/p99 latency, each result's stated error bound);
+`cpu_baseline` times the oracle on the host cores (one steady D = 64 step;
+whole runs at D_cut = 32 and 8 on all cores and on one core).  The dominant kernel
 is the D^7 contraction (C2); its average duration over the steady-state
 steps of the timed runs comes from HIP events recorded on the library's
 stream around each phase.
@@ -60,6 +67,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the FP32 / split-BF16 runs of the same workload")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batch sub-record")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serve sub-record")
+    ap.add_argument("--cpu-baseline-child", type=int, default=0, metavar="THREADS",
+                    help=argparse.SUPPRESS)
     ap.add_argument("--batch", action="store_true",
                     help="the 64-problem XY batch workload instead of the single Ising run")
     ap.add_argument("--serve", type=int, default=0, metavar="N",
@@ -106,7 +117,8 @@ def kernel_probe(args):
 def xy_batch_problems(prec):
     """The XY batch: beta_i = 0.8 + 0.6 i/63 (inclusive grid), n_max = 3 + (i mod 4),
     D_cut = (24, 32, 40, 48)[(i div 4) mod 4], 25 directional steps,
-    multiplet-safe truncation (tau 1e-6 for reduced-precision contractions)."""
+    multiplet-safe truncation with tau = 1e-5 (cuts only at gaps that one
+    rounding cannot move)."""
     from paper_2306_00358_amd import make_opts, model_params
 
     probs = []
@@ -114,7 +126,7 @@ def xy_batch_problems(prec):
         beta = 0.8 + 0.6 * i / 63.0
         n_max = 3 + (i % 4)
         d_cut = (24, 32, 40, 48)[(i // 4) % 4]
-        tau = 1e-10 if prec == "fp64" else 1e-6
+        tau = 1e-5
         probs.append((model_params("xy", beta=beta, n_max=n_max),
                       make_opts(d_cut, 25, prec=prec, trunc="multiplet", degen_tol=tau)))
     return probs
@@ -174,11 +186,12 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def serve_requests(n, seed=0):
+def serve_requests(n, seed=0, tol=0.0):
     """The serving mix: Ising (T uniform in [1.5, 3.5]) or XY (beta uniform in
-    [0.6, 1.6], n_max = 4) with probability 1/2 each, D_cut uniform in
-    {16, 32, 48, 64, 80}, 20-40 directional steps, FP32 or split-BF16 x3
-    contractions; generator PCG64 with the given seed."""
+    [0.6, 1.6], n_max = 4, multiplet tau 1e-5) with probability 1/2 each,
+    D_cut uniform in {16, 32, 48, 64, 80}, 20-40 directional steps, FP32 or
+    split-BF16 x3 contractions with the tolerance `tol` (0: none);
+    generator PCG64 with the given seed."""
     import numpy as np
 
     from paper_2306_00358_amd import make_opts, model_params
@@ -191,9 +204,10 @@ def serve_requests(n, seed=0):
             trunc, tau = "plain", 1e-10
         else:
             p = model_params("xy", beta=rng.uniform(0.6, 1.6), n_max=4)
-            trunc, tau = "multiplet", 1e-6
+            trunc, tau = "multiplet", 1e-5
         o = make_opts(int(rng.choice([16, 32, 48, 64, 80])), int(rng.integers(20, 41)),
-                      prec=str(rng.choice(["fp32", "bf16x3"])), trunc=trunc, degen_tol=tau)
+                      prec=str(rng.choice(["fp32", "bf16x3"])), trunc=trunc, degen_tol=tau,
+                      tol=tol)
         reqs.append((p, o))
     return reqs
 
@@ -329,6 +343,76 @@ def serve_errors(ctx, reqs, vals):
             for k, v in sorted(out.items())}
 
 
+def batch_record(args):
+    """The 64-problem XY batch (FP32 contractions) on the worker pool, timed
+    after one warm-up batch of the first problems."""
+    import torch
+
+    from paper_2306_00358_amd import Context, hotrg_run_batch
+    from paper_2306_00358_amd.flops import dims_schedule, step_flops
+
+    probs = xy_batch_problems("fp32")
+    P = [p for p, _ in probs]
+    O = [o for _, o in probs]
+    flops = sum(sum(step_flops(*d)["total"] for d in dims_schedule(2 * p.n_max + 1, o.d_cut,
+                                                                      o.n_steps))
+                for p, o in probs)
+    n_dir = sum(o.n_steps for o in O)
+    with Context(0) as ctx:
+        ctx.set_workers(args.workers)
+        hotrg_run_batch(ctx, P[:args.workers], O[:args.workers])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res, st = hotrg_run_batch(ctx, P, O)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    log("batch: %d problems in %.2f s" % (len(P), dt))
+    return {"workload": "64 XY problems, beta in [0.8,1.4], n_max 3..6, D_cut in {24,32,40,48}, "
+                        "25 directional steps, fp32 contractions, multiplet tau 1e-5",
+            "engine": "worker pool, %d workers" % args.workers,
+            "steps_per_s": n_dir / dt, "tflops": flops / dt / 1e12, "seconds": dt,
+            "failed": sum(1 for x in st if x != 0)}
+
+
+def serve_record(args, rate_tflops, n=20, tol=1e-7):
+    """A seeded Poisson stream of n mixed requests (the serving mix, each
+    with a stated tolerance of tol against FP64) at 0.8 of the saturation
+    rate estimated from rate_tflops over the mean request's flops."""
+    import numpy as np
+
+    from paper_2306_00358_amd import Context
+    from paper_2306_00358_amd.flops import dims_schedule, step_flops
+
+    reqs = serve_requests(n, seed=0, tol=tol)
+
+    def d0(p):
+        return 2 if p.model == 0 else 2 * p.n_max + 1
+
+    flops = [sum(step_flops(*d)["total"] for d in dims_schedule(d0(p), o.d_cut, o.n_steps))
+             for p, o in reqs]
+    sat = rate_tflops * 1e12 / float(np.mean(flops))
+    rate = 0.8 * sat
+    with Context(0) as ctx:
+        ctx.set_workers(args.workers)
+        vals, dt = serve_stream(ctx, reqs, rate, 1, "serve")
+        stats = ctx.sched_stats()
+    out = stream_summary(reqs, vals, dt, flops)
+    bounds = {}
+    for (p, o), v in zip(reqs, vals):
+        key = "%s/%s" % ({0: "fp64", 1: "fp32", 2: "bf16x3"}[v["prec_used"]],
+                         {0: "ising", 1: "xy"}.get(p.model, "other"))
+        bounds.setdefault(key, []).append(v["err_bound"])
+    out.update({
+        "workload": "seeded Poisson stream of %d Ising/XY requests, D_cut in {16..80}, 20-40 "
+                    "steps, fp32 / split-bf16 contractions with tol %.0e against FP64" % (n, tol),
+        "arrival_rate_per_s": rate, "estimated_saturation_per_s": sat,
+        "admission": stats, "seconds": dt,
+        "stated_error_bound": {k: {"n": len(b), "max": max(b), "median": float(np.median(b))}
+                               for k, b in sorted(bounds.items())},
+    })
+    return out
+
+
 def small_case(ctx, reps=20):
     """The small configuration (Ising at T_c, D_cut = 8, 20 directional steps,
     FP64): launch- and latency-bound; steps/s over `reps` runs."""
@@ -375,6 +459,39 @@ def mid_case(ctx, reps=3):
             "runs": runs}
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_full_runs(threads):
+    """The oracle's whole runs (initial tensor to ln Z / N) of the small and
+    the D_cut = 32 configurations (Ising at T_c), with `threads` BLAS threads
+    (0: all available)."""
+    from threadpoolctl import threadpool_info, threadpool_limits
+
+    from oracle import hotrg, tensors
+
+    out = {}
+    with threadpool_limits(threads if threads > 0 else None):
+        used = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+        for name, d_cut, K in (("d_cut_8", 8, 20), ("d_cut_32", 32, 30)):
+            t0 = time.perf_counter()
+            r = hotrg.run(tensors.ising(BETA_C), d_cut, K)
+            dt = time.perf_counter() - t0
+            out[name] = {"seconds": dt, "steps_per_s": K / dt, "threads": used,
+                         "lnz_per_site": r.lnz_per_site,
+                         "workload": "Ising T_c, D_cut=%d, %d directional steps, init to ln Z/N"
+                                     % (d_cut, K)}
+    return out
+
+
 def cpu_baseline(d_cut):
     """The oracle on the host cores: one steady-state directional step at
     dims (d_cut, d_cut, d_cut) of the same Ising run (the warm-up steps that
@@ -416,6 +533,20 @@ def main():
         print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(--gpus %d, WORLD_SIZE %d)" % (args.gpus, world), file=sys.stderr)
         sys.exit(2)
+    if args.cpu_baseline_child:
+        # the oracle's whole runs on a fixed number of host threads (no GPU)
+        print(json.dumps(cpu_full_runs(args.cpu_baseline_child)), flush=True)
+        return
+    child = None
+    if not (args.no_cpu_baseline or args.kernel_probe or args.batch or args.serve):
+        # the one-core oracle runs overlap the GPU measurements: a child
+        # process started before this one touches the GPU
+        import subprocess
+
+        env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1")
+        child = subprocess.Popen([sys.executable, os.path.abspath(__file__),
+                                  "--cpu-baseline-child", "1"], stdout=subprocess.PIPE,
+                                 stderr=subprocess.DEVNULL, env=env, text=True)
 
     import torch
 
@@ -445,35 +576,42 @@ def main():
         with open(golden) as f:
             ref = json.load(f)["runs"][0]["steps"][args.n_steps - 1]["lnz_torus"]
 
-    def measure(prec):
-        opts = make_opts(args.d_cut, args.n_steps, prec=prec, spec_len=0)
-        for _ in range(args.warmup):
+    def measure(prec, runs=None, warmup=None, tol=0.0):
+        runs = args.steps if runs is None else runs
+        warmup = args.warmup if warmup is None else warmup
+        opts = make_opts(args.d_cut, args.n_steps, prec=prec, spec_len=0, tol=tol)
+        for _ in range(warmup):
             hotrg_run(ctx, params, opts)
         ctx.timings()  # discard
         ctx.enable_timing(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        results = [hotrg_run(ctx, params, opts) for _ in range(args.steps)]
+        results = [hotrg_run(ctx, params, opts) for _ in range(runs)]
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
         ctx.enable_timing(False)
         recs = ctx.timings()
+        log("%s%s: %d runs in %.2f s" % (prec, " tol %.0e" % tol if tol else "", runs, elapsed))
         c2 = [r["ms"] for r in recs
               if r["phase"] == "c2" and (r["dx"], r["dy"], r["d_new"]) == steady]
         phase_ms = {}
         for r in recs:
-            phase_ms[r["phase"]] = phase_ms.get(r["phase"], 0.0) + r["ms"] / args.steps
+            phase_ms[r["phase"]] = phase_ms.get(r["phase"], 0.0) + r["ms"] / runs
         c2_ms = sum(c2) / len(c2) if c2 else float("nan")
         achieved = step_flops(*steady)["c2"] / (c2_ms * 1e-3) / 1e12
         lnz = results[-1]["lnz_per_site"]
-        tflops = flops_run * args.steps / elapsed / 1e12
-        issued = 3.0 if prec == "bf16x3" else 1.0  # bf16 products per multiply-add
+        tflops = flops_run * runs / elapsed / 1e12
+        pu = {0: "fp64", 1: "fp32", 2: "bf16x3"}[results[-1]["prec_used"]]
+        issued = 3.0 if pu == "bf16x3" else 1.0  # bf16 products per multiply-add
         return {
-            "steps_per_s": args.n_steps * args.steps / elapsed,
-            "ms_per_run": elapsed / args.steps * 1e3,
+            "runs": runs,
+            "prec_used": pu,
+            "err_bound": results[-1]["err_bound"],
+            "steps_per_s": args.n_steps * runs / elapsed,
+            "ms_per_run": elapsed / runs * 1e3,
             "tflops": tflops,
             # whole run: issued MFMA flops over run time x peak (eigensolver included)
-            "run_frac_of_peak": issued * tflops / PEAKS[prec],
+            "run_frac_of_peak": issued * tflops / PEAKS[pu],
             "eigh_share": phase_ms.get("eigh", 0.0) / (elapsed / args.steps * 1e3),
             "lnz_per_site": lnz,
             "rel_err_vs_fp64_oracle": abs(lnz - ref) / abs(ref) if ref is not None else None,
@@ -492,6 +630,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": head["ms_per_run"],
+        "bench_step": "one whole run of %d directional steps" % args.n_steps,
+        "ms_per_directional_step": head["ms_per_run"] / args.n_steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -520,23 +660,46 @@ def main():
         # the same workload with reduced-precision contractions (eigensolver
         # and log-norm stay FP64)
         mixed = {}
+        runs = min(args.steps, 5)
         for prec in ("fp32", "bf16x3"):
             if prec == args.prec:
                 continue
-            m = measure(prec)
+            m = measure(prec, runs=runs, warmup=1)
             m["speedup_vs_" + args.prec] = m["steps_per_s"] / head["steps_per_s"]
             m["c2_frac_of_peak"] = m["c2_tflops"] / PEAKS[prec]
             if prec == "bf16x3":
                 # three bf16 products are issued per multiply-add
                 m["c2_issued_frac_of_peak"] = 3 * m["c2_tflops"] / PEAKS[prec]
             mixed[prec] = m
+        # the cheapest precision whose stated bound meets 1e-7 (leading steps
+        # FP64, the rest reduced)
+        m = measure("auto", runs=runs, warmup=1, tol=1e-7)
+        m["speedup_vs_" + args.prec] = m["steps_per_s"] / head["steps_per_s"]
+        for k in ("c2_ms", "c2_launches", "c2_tflops"):
+            m.pop(k)  # C2 launches of two precisions
+        mixed["auto_tol_1e-7"] = m
         out["mixed_vs_" + args.prec] = mixed
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.d_cut)
-        # the oracle at the D_cut = 32 configuration too (one steady step)
-        out["cpu_baseline"]["d_cut_32"] = cpu_baseline(32)
-    print(json.dumps(out), flush=True)
     ctx.close()
+    if not args.no_batch:
+        out["batch"] = batch_record(args)
+    if not args.no_serve:
+        rate = (out.get("mixed_vs_" + args.prec, {}).get("auto_tol_1e-7", {}).get("tflops")
+                or head["tflops"])
+        out["serve"] = serve_record(args, rate)
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline(args.d_cut)
+        cb["cpu_model"] = cpu_model()
+        cb["full_runs_all_cores"] = cpu_full_runs(0)
+        one = None
+        if child is not None:
+            try:
+                one = json.loads(child.communicate(timeout=600)[0].strip().splitlines()[-1])
+            except Exception as e:  # noqa: BLE001 - reported, not fatal
+                child.kill()
+                one = {"error": str(e)}
+        cb["full_runs_one_core"] = one
+        out["cpu_baseline"] = cb
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":
