@@ -344,11 +344,13 @@ def serve_errors(ctx, reqs, vals):
 
 
 def batch_record(args):
-    """The 64-problem XY batch (FP32 contractions) on the worker pool, timed
-    after one warm-up batch of the first problems."""
+    """The 64-problem XY batch (FP32 contractions): in lockstep (grouped
+    launches, one HIP graph per sweep; after one untimed batch that tunes the
+    grouped tiles) and on the worker pool (after a warm-up batch of the first
+    problems), each result of the lockstep run against the pool's."""
     import torch
 
-    from paper_2306_00358_amd import Context, hotrg_run_batch
+    from paper_2306_00358_amd import Context, hotrg_run_batch, hotrg_run_grouped
     from paper_2306_00358_amd.flops import dims_schedule, step_flops
 
     probs = xy_batch_problems("fp32")
@@ -359,19 +361,38 @@ def batch_record(args):
                 for p, o in probs)
     n_dir = sum(o.n_steps for o in O)
     with Context(0) as ctx:
+        hotrg_run_grouped(ctx, P, O)
+        torch.cuda.synchronize()
+        s0 = ctx.group_stats()
+        t0 = time.perf_counter()
+        res_g, st_g = hotrg_run_grouped(ctx, P, O)
+        torch.cuda.synchronize()
+        dt_g = time.perf_counter() - t0
+        s1 = ctx.group_stats()
+    log("batch, lockstep: %d problems in %.2f s" % (len(P), dt_g))
+    with Context(0) as ctx:
         ctx.set_workers(args.workers)
         hotrg_run_batch(ctx, P[:args.workers], O[:args.workers])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        res, st = hotrg_run_batch(ctx, P, O)
+        res_p, st_p = hotrg_run_batch(ctx, P, O)
         torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-    log("batch: %d problems in %.2f s" % (len(P), dt))
+        dt_p = time.perf_counter() - t0
+    log("batch, worker pool: %d problems in %.2f s" % (len(P), dt_p))
+    diff = [abs(a["lnz_per_site"] - b["lnz_per_site"]) / abs(b["lnz_per_site"])
+            for a, b in zip(res_g, res_p) if a and b]
+    stats = {k: s1[k] - s0[k] for k in s1}
     return {"workload": "64 XY problems, beta in [0.8,1.4], n_max 3..6, D_cut in {24,32,40,48}, "
                         "25 directional steps, fp32 contractions, multiplet tau 1e-5",
-            "engine": "worker pool, %d workers" % args.workers,
-            "steps_per_s": n_dir / dt, "tflops": flops / dt / 1e12, "seconds": dt,
-            "failed": sum(1 for x in st if x != 0)}
+            "engine": "lockstep: grouped launches, batched eigensolver, one HIP graph per sweep",
+            "steps_per_s": n_dir / dt_g, "tflops": flops / dt_g / 1e12, "seconds": dt_g,
+            "failed": sum(1 for x in st_g if x != 0), "graph": stats,
+            "worker_pool": {"workers": args.workers, "steps_per_s": n_dir / dt_p,
+                            "tflops": flops / dt_p / 1e12, "seconds": dt_p,
+                            "failed": sum(1 for x in st_p if x != 0)},
+            "speedup_vs_worker_pool": dt_p / dt_g,
+            "max_rel_diff_vs_worker_pool": max(diff) if diff else None,
+            "max_stated_error_bound": max(r["err_bound"] for r in res_g if r)}
 
 
 def serve_record(args, rate_tflops, n=20, tol=1e-7):

@@ -245,6 +245,32 @@ hotrg_status hotrg_run_batch(hotrg_ctx* ctx, int n, const hotrg_model_params* pa
                              const hotrg_opts* opts, hotrg_result* results,
                              hotrg_status* statuses);
 
+/* Run n problems in lockstep on the context's own stream (the paper's
+ * studies scan many temperatures and couplings, Sec. 3.1-3.3): every problem
+ * takes its warm-up steps alone, then all of them advance one steady-state
+ * directional step per sweep, each phase of the sweep one launch over every
+ * problem -- grouped MFMA GEMMs reading a device table of the problems'
+ * products (uneven D_cut and shapes), a batched block eigensolver (subspace
+ * iteration with a fixed budget of rounds, Rayleigh-Ritz by a parallel Jacobi
+ * method, one workgroup per problem), batched bookkeeping -- and the whole
+ * sweep is captured once as a HIP graph and replayed (captured again when a
+ * problem has finished its steps).  Grouped launches pick their tile shapes by
+ * timing the candidates on the first sweep of a set of shapes.  A problem
+ * joins the batch when its steady state has D' + 17 <= p <= 128 and 4p <= D'^2
+ * (p = the eigensolver's block size, about 2 D'), the one-sided isometry, the
+ * automatic eigensolver choice and the batch's steady precision; other
+ * problems run whole, one after another, before the batch.  A problem whose
+ * batched eigensolve does not converge within the budget is run again alone.
+ * Results are as hotrg_run's (to rounding: another summation order).  `results`
+ * and `statuses` as for hotrg_run_batch; returns the first failure or OK. */
+hotrg_status hotrg_run_grouped(hotrg_ctx* ctx, int n, const hotrg_model_params* params,
+                               const hotrg_opts* opts, hotrg_result* results,
+                               hotrg_status* statuses);
+/* Counters of hotrg_run_grouped on this context: sweeps run, of them graph
+ * replays, graph captures, problems re-run alone. */
+hotrg_status hotrg_ctx_group_stats(hotrg_ctx* ctx, uint64_t* sweeps, uint64_t* replays,
+                                   uint64_t* captures, uint64_t* fallbacks);
+
 /* Internal energy and specific heat per site by finite differences of ln Z/N
  * in beta (Sec. 3.3 obtains the specific heat as a finite-difference second
  * derivative of ln Z): the problem of `params` / `opts` is run at

@@ -30,7 +30,8 @@ EXPORTS = [
     "hotrg_run", "hotrg_environment", "hotrg_coarse", "hotrg_ctx_enable_timing", "hotrg_ctx_timings",
     "hotrg_ctx_set_workers", "hotrg_submit", "hotrg_poll", "hotrg_wait", "hotrg_cancel",
     "hotrg_footprint", "hotrg_run_batch", "hotrg_ctx_sched_stats", "hotrg_thermo",
-    "hotrg_release", "hotrg_coarse_noalloc", "hotrg_plan",
+    "hotrg_release", "hotrg_coarse_noalloc", "hotrg_plan", "hotrg_run_grouped",
+    "hotrg_ctx_group_stats",
 ]
 
 NOALLOC_SCRATCH_BYTES = 64 << 20  # HOTRG_NOALLOC_SCRATCH_BYTES
@@ -119,6 +120,9 @@ def lib():
                              POINTER(c_double)]
     L.hotrg_run_batch.argtypes = [vp, c_int, POINTER(ModelParams), POINTER(Opts), POINTER(Result),
                                   POINTER(c_int)]
+    L.hotrg_run_grouped.argtypes = [vp, c_int, POINTER(ModelParams), POINTER(Opts),
+                                    POINTER(Result), POINTER(c_int)]
+    L.hotrg_ctx_group_stats.argtypes = [vp] + [POINTER(ctypes.c_uint64)] * 4
     L.hotrg_ctx_sched_stats.argtypes = [vp, POINTER(ctypes.c_uint64), POINTER(ctypes.c_uint64),
                                         POINTER(c_size_t)]
     L.hotrg_ctx_timings.argtypes = [vp, POINTER(PhaseTime), c_int]
@@ -205,6 +209,11 @@ class Context:
         a, st, pk = ctypes.c_uint64(), ctypes.c_uint64(), c_size_t()
         _check(lib().hotrg_ctx_sched_stats(self.ptr, byref(a), byref(st), byref(pk)))
         return {"admitted": a.value, "stalls": st.value, "peak_reserved": pk.value}
+
+    def group_stats(self):
+        v = [ctypes.c_uint64() for _ in range(4)]
+        _check(lib().hotrg_ctx_group_stats(self.ptr, *[byref(x) for x in v]))
+        return dict(zip(("sweeps", "replays", "captures", "fallbacks"), (x.value for x in v)))
 
     def enable_timing(self, on=True):
         _check(lib().hotrg_ctx_enable_timing(self.ptr, 1 if on else 0))
@@ -331,7 +340,13 @@ def hotrg_footprint(params, opts):
     return b.value
 
 
-def hotrg_run_batch(ctx, params_list, opts_list, with_steps=False):
+def hotrg_run_grouped(ctx, params_list, opts_list, with_steps=False):
+    """Run problems in lockstep (grouped launches, one graph per sweep);
+    returns (list of result dicts or None for failed problems, statuses)."""
+    return hotrg_run_batch(ctx, params_list, opts_list, with_steps, _fn="hotrg_run_grouped")
+
+
+def hotrg_run_batch(ctx, params_list, opts_list, with_steps=False, _fn="hotrg_run_batch"):
     """Run problems on the context's worker pool; returns (list of result
     dicts or None for failed problems, list of statuses)."""
     n = len(params_list)
@@ -349,7 +364,7 @@ def hotrg_run_batch(ctx, params_list, opts_list, with_steps=False):
         else:
             keep.append((None, None))
     S = (c_int * n)()
-    lib().hotrg_run_batch(ctx.ptr, n, P, O, R, S)
+    getattr(lib(), _fn)(ctx.ptr, n, P, O, R, S)
     out = []
     for i in range(n):
         if S[i] != HOTRG_OK:

@@ -18,7 +18,7 @@ LIB = os.path.join(PKG, "libhotrg.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.path.join(ROCM, "bin", "hipcc")
 
-SOURCES = ["engine.hip", "eigs.hip", "gemm.hip", "gemm_lds.hip", "gemm_rp.hip", "kernels.hip",
+SOURCES = ["engine.hip", "eigs.hip", "gemm.hip", "gemm_lds.hip", "gemm_rp.hip", "group.hip", "kernels.hip",
            "models.cpp", "noalloc.hip", "sched.cpp"]
 
 CFLAGS = [

@@ -84,11 +84,9 @@ __global__ void k_seed_block(double* V, long long count, unsigned long long seed
 // LDS for coalesced stores.  *fail is set if a pivot is not positive.
 constexpr int kCholThreads = 256;
 
-__global__ __launch_bounds__(kCholThreads) void k_chol_inv(const double* __restrict__ G, int p,
-                                                           double shift_rel, int scale,
-                                                           double identity_tol,
-                                                           double* __restrict__ RinvT,
-                                                           int* fail) {
+__device__ __forceinline__ void chol_inv_body(const double* __restrict__ G, int p,
+                                              double shift_rel, int scale, double identity_tol,
+                                              double* __restrict__ RinvT, int* fail) {
   extern __shared__ double lds[];
   double* R = lds;             // p * p: R (upper, zeros below), later X^T
   double* P = R + p * p;       // 2 x 8 x 128 published rows
@@ -329,6 +327,37 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_inv(const double* __restr
     }
   __syncthreads();
   for (int e = t; e < p * p; e += kCholThreads) RinvT[e] = R[e];
+}
+
+__global__ __launch_bounds__(kCholThreads) void k_chol_inv(const double* __restrict__ G, int p,
+                                                           double shift_rel, int scale,
+                                                           double identity_tol,
+                                                           double* __restrict__ RinvT,
+                                                           int* fail) {
+  chol_inv_body(G, p, shift_rel, scale, identity_tol, RinvT, fail);
+}
+
+// One workgroup per problem of a batch; a problem whose gate reads 0 (its
+// eigensolve has converged, or it has no steps left) is skipped.
+__global__ __launch_bounds__(kCholThreads) void k_chol_inv_b(const CholItem* __restrict__ items,
+                                                             int pass, int full) {
+  const CholItem& it = items[blockIdx.x];
+  if (it.gate && *it.gate == 0) return;
+  chol_inv_body(it.G, it.p, pass < 2 ? it.shift_rel : 0.0, pass < 2 ? 1 : 0,
+                (pass == 0 || full) ? 0.0 : 1e-2, it.Rt, it.fail);
+}
+
+void launch_chol_inv_batched(const CholItem* d_items, int count, int pmax, int pass, bool full,
+                             hipStream_t s) {
+  static bool lds_set = [] {
+    return hipFuncSetAttribute((const void*)k_chol_inv_b,
+                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)(((size_t)128 * 128 + 2048) * sizeof(double))) == hipSuccess;
+  }();
+  (void)lds_set;
+  const size_t lds = ((size_t)pmax * pmax + 2048) * sizeof(double);
+  hipLaunchKernelGGL(k_chol_inv_b, dim3(count), dim3(kCholThreads), lds, s, d_items, pass,
+                     full ? 1 : 0);
 }
 
 __global__ void k_symmetrize_small(double* H, int p) {

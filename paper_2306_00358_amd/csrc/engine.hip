@@ -18,6 +18,8 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -93,6 +95,9 @@ struct hotrg_ctx {
   // eigensolve of this step number reports failure, as a non-zero rocSOLVER
   // info would; 0: off
   int test_fail_step = 0;
+  // lockstep batches: sweeps run, of them graph replays, graph captures,
+  // problems re-run alone after their batched eigensolve failed
+  uint64_t g_sweeps = 0, g_replays = 0, g_captures = 0, g_fallbacks = 0;
   // per-phase timing
   bool timing = false;
   struct Mark {
@@ -505,13 +510,8 @@ void coarse_rp(hotrg_ctx* c, hotrg_state* st, int mode, int dx, int dy, int dn,
   if (!ok) fail(HOTRG_ERR_INVALID, "reduced-precision contraction: unsupported operand shape");
 }
 
-void do_step(hotrg_ctx* c, hotrg_state* st, const hotrg_opts* o) {
-  const int dx = st->dx, dy = st->dy;
-  const int n = dx * dx;
-  const int dn = o->d_cut < n ? o->d_cut : n;
-  check_dims(dx, dy, dn);
-  const int k = st->k + 1;
-  // per-step records and spectra
+// Records and spectra of steps 1..k (device), spectra of spec_len values.
+void reserve_records(hotrg_ctx* c, hotrg_state* st, int k, int spec_len) {
   if (k > st->rec_cap) {
     int cap = st->rec_cap ? 2 * st->rec_cap : 64;
     while (cap < k) cap *= 2;
@@ -520,12 +520,21 @@ void do_step(hotrg_ctx* c, hotrg_state* st, const hotrg_opts* o) {
       ensure_keep(c, st->spec, (size_t)cap * st->spec_len * 8, (size_t)st->rec_cap * st->spec_len * 8);
     st->rec_cap = cap;
   }
-  if (o->spec_len != st->spec_len) {
+  if (spec_len != st->spec_len) {
     if (st->k > 0 && st->spec_len != 0)
       fail(HOTRG_ERR_INVALID, "spec_len must not change between steps of one state");
-    st->spec_len = o->spec_len;
+    st->spec_len = spec_len;
     if (st->spec_len) ensure(c, st->spec, (size_t)st->rec_cap * st->spec_len * 8);
   }
+}
+
+void do_step(hotrg_ctx* c, hotrg_state* st, const hotrg_opts* o) {
+  const int dx = st->dx, dy = st->dy;
+  const int n = dx * dx;
+  const int dn = o->d_cut < n ? o->d_cut : n;
+  check_dims(dx, dy, dn);
+  const int k = st->k + 1;
+  reserve_records(c, st, k, o->spec_len);
   double* rec = (double*)st->recs.p + kRec * (size_t)(k - 1);
   double* spec = st->spec_len ? (double*)st->spec.p + (size_t)(k - 1) * st->spec_len : nullptr;
   ensure(c, c->scal, 64);
@@ -776,6 +785,682 @@ hotrg_status guard(F&& f) {
     g_err = e.what();
     return HOTRG_ERR_DEVICE;
   }
+}
+
+}  // namespace
+
+namespace {
+
+// ------------------------------------------------------ lockstep batches --
+// hotrg_run_grouped: the problems of a batch take their steady-state steps
+// together, each phase one launch over all of them (grouped GEMMs over a
+// device table of products, batched eigensolver and bookkeeping kernels), and
+// the whole sweep is captured once as a HIP graph and replayed.
+
+constexpr int kGroupRounds = 7;          // Rayleigh-Ritz checks per step
+constexpr int kGroupSweepsPerRound = 4;  // subspace sweeps before each check
+constexpr double kGroupTol = 5e-14;      // residual tolerance (as do_step's solver)
+
+struct GProb {
+  int idx = 0;          // position in the caller's arrays
+  hotrg_opts o{};       // options with the precision resolved
+  hotrg_state* st = nullptr;
+  std::vector<int> dxs, dys, dns;
+  int D = 0, n = 0, p = 0, need = 0, sp = HOTRG_FP64;  // steady dims, block size, precision
+  Buf M, eig, U, scal, Tt, U1, U3;
+  Buf RA1[2], RA2[2], RX1[2], RX2[2], RU1[2], RU3[2];
+  GroupCtl* ctl = nullptr;  // device
+  int k_host = 0;           // steps done, as the host counts them
+  double t0 = 0.0;
+};
+
+struct GTable {  // a grouped launch's device table
+  char* items = nullptr;
+  int* begin[3] = {nullptr, nullptr, nullptr};  // per tile configuration (reduced precision)
+  int count = 0, tiles[3] = {0, 0, 0};
+};
+
+struct GRun {
+  std::vector<GProb*> act;
+  int sp = HOTRG_FP64, mode = RP_F32, pmax = 16;
+  long long max_pn = 1;
+  GroupStep* steps = nullptr;
+  CholItem* chol = nullptr;
+  // eigensolver products
+  GTable vm, gramY, gramT2, apYT2, apT2V, apT2Y, apYV, rrH, rrX, rrYx;
+  // reduced-precision contractions and their tile configuration
+  GTable halves, combine, c1, c2, c3;
+  int cfg[5] = {-1, -1, -1, -1, -1};
+};
+
+void launch_f64_table(const GTable& t, int bl, hipStream_t s) {
+  gemm_f64_grouped(bl, (const F64Item*)t.items, t.begin[0], t.count, t.tiles[0], s);
+}
+
+void launch_rp_table(const GTable& t, int mode, int out, int cfg, hipStream_t s) {
+  gemm_rp_grouped(mode, out, cfg, (const RpItem*)t.items, t.begin[cfg], t.count, t.tiles[cfg], s);
+}
+
+// tile configurations chosen for grouped reduced-precision launches, by the
+// shapes of their products (the tuner of the lockstep engine)
+std::mutex g_gtune_mu;
+std::map<std::vector<long long>, int> g_gtune;
+
+std::vector<long long> table_key(int mode, int op, const std::vector<RpItem>& items) {
+  std::vector<long long> k = {mode, op};
+  for (const RpItem& it : items) {
+    k.push_back(it.M);
+    k.push_back(it.N);
+    k.push_back(it.K);
+  }
+  return k;
+}
+
+// One steady sweep of every active problem (captured or eager).  With
+// `tune`, each grouped reduced-precision launch without a recorded tile
+// configuration times the three candidates first (they all write the same
+// products; C3's max is idempotent).
+void group_sweep(hotrg_ctx* c, GRun& R, bool tune, std::vector<std::vector<long long>>* keys) {
+  hipStream_t s = c->stream;
+  const int G = (int)R.act.size();
+  const bool red = R.sp != HOTRG_FP64;
+  const int split = R.mode == RP_BF16X3;
+  // environment M of every problem
+  if (red) {
+    const int outs[2] = {split ? RP_OUT_SPLIT : RP_OUT_F32, RP_OUT_F64};
+    GTable* tabs[2] = {&R.halves, &R.combine};
+    for (int q = 0; q < 2; ++q) {
+      if (tune && R.cfg[q] < 0) {
+        hipEvent_t a, b;
+        HIPCHK(hipEventCreate(&a));
+        HIPCHK(hipEventCreate(&b));
+        float best = 0.f;
+        for (int cf = 0; cf < 3; ++cf) {
+          float ms = 0.f;
+          for (int rep = 0; rep < 2; ++rep) {
+            HIPCHK(hipEventRecord(a, s));
+            launch_rp_table(*tabs[q], R.mode, outs[q], cf, s);
+            HIPCHK(hipEventRecord(b, s));
+            HIPCHK(hipEventSynchronize(b));
+            float t = 0.f;
+            HIPCHK(hipEventElapsedTime(&t, a, b));
+            ms = rep == 0 ? t : std::min(ms, t);
+          }
+          if (R.cfg[q] < 0 || ms < best) {
+            best = ms;
+            R.cfg[q] = cf;
+          }
+        }
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        std::lock_guard<std::mutex> lk(g_gtune_mu);
+        g_gtune[(*keys)[q]] = R.cfg[q];
+      }
+      launch_rp_table(*tabs[q], R.mode, outs[q], R.cfg[q], s);
+    }
+  } else {
+    for (GProb* g : R.act)
+      environment_f64(c, (const double*)g->st->Tn.p, (const double*)g->st->Xt.p, g->D, g->D, &g->M);
+  }
+  for (GProb* g : R.act) {
+    launch_symmetrize((double*)g->M.p, g->n, s);
+    launch_trace((const double*)g->M.p, g->n, (double*)((char*)g->scal.p + 8), s);
+  }
+  // leading eigenpairs: block subspace iteration with a fixed budget
+  group_begin(R.steps, G, s);
+  group_seed(R.steps, G, R.max_pn, s);
+  auto pass = [&](const GTable& gram, int ps, bool full, const GTable& apply) {
+    launch_f64_table(gram, B_KCONTIG, s);
+    launch_chol_inv_batched(R.chol, G, R.pmax, ps, full, s);
+    launch_f64_table(apply, B_NCONTIG, s);
+  };
+  for (int round = 0; round < kGroupRounds; ++round) {
+    for (int sw = 0; sw < kGroupSweepsPerRound; ++sw) {
+      const bool full = sw == kGroupSweepsPerRound - 1;
+      launch_f64_table(R.vm, B_NCONTIG, s);  // Y = V M
+      pass(R.gramY, 0, full, R.apYT2);
+      if (full) {
+        pass(R.gramT2, 1, full, R.apT2Y);
+        pass(R.gramY, 2, full, R.apYV);
+      } else {
+        pass(R.gramT2, 1, full, R.apT2V);
+      }
+    }
+    launch_f64_table(R.vm, B_NCONTIG, s);    // Y = V M
+    launch_f64_table(R.rrH, B_KCONTIG, s);   // H = V Y^T
+    group_symm_h(R.steps, G, s);
+    group_jacobi(R.steps, G, R.pmax, s);     // H <- Z^T, W ascending
+    launch_f64_table(R.rrX, B_NCONTIG, s);   // X = Z^T V
+    launch_f64_table(R.rrYx, B_NCONTIG, s);  // Yx = Z^T Y
+    group_resid(R.steps, G, round == kGroupRounds - 1, s);
+    if (round + 1 < kGroupRounds) group_restart(R.steps, G, R.max_pn, s);
+  }
+  // projector
+  group_spectrum(R.steps, G, s);
+  for (GProb* g : R.act) {
+    const int* kept = (const int*)((char*)g->scal.p + 16);
+    launch_isometry((const double*)((double*)g->eig.p + 4LL * g->p * g->n), g->p, g->n, g->D, kept,
+                    (double*)g->U.p, s);
+    if (red) {
+      const long long ldx = pad32(g->D), ldn = pad32(g->n);
+      launch_layout_u_rp((const double*)g->U.p, g->D, g->D, R.mode, g->RU1[0].p,
+                         split ? g->RU1[1].p : nullptr, g->RU3[0].p, split ? g->RU3[1].p : nullptr,
+                         ldx, ldn, s);
+    } else {
+      launch_layout_u((const double*)g->U.p, g->D, g->D, g->U1.p, g->U3.p, false, s);
+    }
+  }
+  // the three contractions, max|T~|
+  if (red) {
+    group_zero_max(R.steps, G, s);
+    GTable* tabs[3] = {&R.c1, &R.c2, &R.c3};
+    const int outs[3] = {split ? RP_OUT_SPLIT : RP_OUT_F32, split ? RP_OUT_SPLIT : RP_OUT_F32,
+                         RP_OUT_F32};
+    for (int q = 0; q < 3; ++q) {
+      if (tune && R.cfg[2 + q] < 0) {
+        hipEvent_t a, b;
+        HIPCHK(hipEventCreate(&a));
+        HIPCHK(hipEventCreate(&b));
+        float best = 0.f;
+        for (int cf = 0; cf < 3; ++cf) {
+          float ms = 0.f;
+          for (int rep = 0; rep < 2; ++rep) {
+            HIPCHK(hipEventRecord(a, s));
+            launch_rp_table(*tabs[q], R.mode, outs[q], cf, s);
+            HIPCHK(hipEventRecord(b, s));
+            HIPCHK(hipEventSynchronize(b));
+            float t = 0.f;
+            HIPCHK(hipEventElapsedTime(&t, a, b));
+            ms = rep == 0 ? t : std::min(ms, t);
+          }
+          if (R.cfg[2 + q] < 0 || ms < best) {
+            best = ms;
+            R.cfg[2 + q] = cf;
+          }
+        }
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        std::lock_guard<std::mutex> lk(g_gtune_mu);
+        g_gtune[(*keys)[2 + q]] = R.cfg[2 + q];
+      }
+      launch_rp_table(*tabs[q], R.mode, outs[q], R.cfg[2 + q], s);
+    }
+  } else {
+    for (GProb* g : R.act)
+      coarse_f64_into(c, (const double*)g->st->Tn.p, (const double*)g->st->Tp.p,
+                      (const double*)g->U1.p, (const double*)g->U3.p, g->D, g->D, g->D,
+                      (double*)c->X1.p, (double*)c->X2.p, (double*)g->Tt.p,
+                      (unsigned long long*)g->scal.p, 0);  // shapes tuned by the eager sweep
+  }
+  // ln n_k, torus estimate; operands of the next step (legs transposed)
+  group_norm(R.steps, G, s);
+  for (GProb* g : R.act) {
+    const unsigned long long* mb = (const unsigned long long*)g->scal.p;
+    if (red) {
+      RpOps ops;
+      for (int i = 0; i < 4; ++i) {
+        ops.hi[i] = g->st->RO[i][0].p;
+        ops.lo[i] = split ? g->st->RO[i][1].p : nullptr;
+      }
+      launch_prep_rp(g->Tt.p, true, true, g->D, g->D, mb, (float*)g->st->Tn32.p, R.mode, ops,
+                     pad32((long long)g->D * g->D), pad32(g->D), s);
+    } else {
+      launch_prep(g->Tt.p, false, true, g->D, g->D, mb, g->st->Tn.p, g->st->Xt.p, g->st->Tp.p,
+                  false, s);
+    }
+  }
+  group_advance(R.steps, G, s);
+}
+
+// Device tables of the active problems (items ordered as R.act).
+void group_tables(hotrg_ctx* c, GRun& R, Buf& store, std::vector<std::vector<long long>>* keys) {
+  const int G = (int)R.act.size();
+  std::vector<char> host;
+  auto put = [&](const void* p, size_t bytes) {
+    const size_t off = (host.size() + 255) / 256 * 256;
+    host.resize(off + bytes);
+    std::memcpy(host.data() + off, p, bytes);
+    return off;
+  };
+  struct Pending {
+    GTable* t;
+    size_t items;
+    size_t begin[3];
+  };
+  std::vector<Pending> pend;
+  auto f64tab = [&](GTable& t, auto make) {
+    std::vector<F64Item> it;
+    std::vector<int> b(1, 0);
+    for (GProb* g : R.act) {
+      it.push_back(make(g));
+      b.push_back(b.back() + f64_group_tiles(it.back()));
+    }
+    t.count = G;
+    t.tiles[0] = b.back();
+    b.pop_back();
+    pend.push_back({&t, put(it.data(), it.size() * sizeof(F64Item)),
+                    {put(b.data(), b.size() * sizeof(int)), 0, 0}});
+  };
+  auto rptab = [&](GTable& t, const std::vector<RpItem>& it, int op) {
+    Pending pe{&t, put(it.data(), it.size() * sizeof(RpItem)), {0, 0, 0}};
+    for (int cf = 0; cf < 3; ++cf) {
+      std::vector<int> b(1, 0);
+      for (const RpItem& x : it) b.push_back(b.back() + rp_group_tiles(x, cf));
+      t.tiles[cf] = b.back();
+      b.pop_back();
+      pe.begin[cf] = put(b.data(), b.size() * sizeof(int));
+    }
+    t.count = (int)it.size();
+    pend.push_back(pe);
+    keys->push_back(table_key(R.mode, op, it));
+  };
+  // descriptors
+  std::vector<GroupStep> st;
+  std::vector<CholItem> ch;
+  for (GProb* g : R.act) {
+    const long long pn = (long long)g->p * g->n, pp = (long long)g->p * g->p;
+    double* e = (double*)g->eig.p;
+    GroupStep d{};
+    d.ctl = g->ctl;
+    d.n = g->n;
+    d.dn = g->D;
+    d.dy = g->D;
+    d.p = g->p;
+    d.need = g->need;
+    d.trunc = g->o.trunc;
+    d.spec_len = g->st->spec_len;
+    d.K = g->o.n_steps;
+    d.tau = g->o.degen_tol;
+    d.tol = kGroupTol;
+    d.V = e;
+    d.Y = e + pn;
+    d.T2 = e + 2 * pn;
+    d.Yx = e + 3 * pn;
+    d.X = e + 4 * pn;
+    d.G = e + 5 * pn;
+    d.Rt = d.G + pp;
+    d.H = d.Rt + pp;
+    d.W = d.H + pp;
+    d.res = d.W + g->p;
+    d.trace = (double*)((char*)g->scal.p + 8);
+    d.kept = (int*)((char*)g->scal.p + 16);
+    d.maxbits = (unsigned long long*)g->scal.p;
+    d.recs = (double*)g->st->recs.p;
+    d.spec = (double*)g->st->spec.p;
+    d.acc = (double*)g->st->acc.p;
+    d.Tt = g->Tt.p;
+    d.tt_f32 = R.sp != HOTRG_FP64;
+    st.push_back(d);
+    CholItem ci{d.G, d.Rt, &g->ctl->fail, &g->ctl->iter, g->p,
+                11.0 * ((double)g->n * g->p + (double)g->p * (g->p + 1)) * std::ldexp(1.0, -53)};
+    ch.push_back(ci);
+  }
+  const size_t o_steps = put(st.data(), st.size() * sizeof(GroupStep));
+  const size_t o_chol = put(ch.data(), ch.size() * sizeof(CholItem));
+  auto stp = [&](GProb* g) {
+    for (size_t i = 0; i < R.act.size(); ++i)
+      if (R.act[i] == g) return st[i];
+    return st[0];
+  };
+  auto item = [&](const double* A, long long lda, const double* B, long long ldb, double* C,
+                  long long ldc, int M, int N, int K, GProb* g) {
+    return F64Item{A, lda, B, ldb, C, ldc, M, N, K, &g->ctl->iter};
+  };
+  f64tab(R.vm, [&](GProb* g) { auto d = stp(g); return item(d.V, g->n, (const double*)g->M.p, g->n, d.Y, g->n, g->p, g->n, g->n, g); });
+  f64tab(R.gramY, [&](GProb* g) { auto d = stp(g); return item(d.Y, g->n, d.Y, g->n, d.G, g->p, g->p, g->p, g->n, g); });
+  f64tab(R.gramT2, [&](GProb* g) { auto d = stp(g); return item(d.T2, g->n, d.T2, g->n, d.G, g->p, g->p, g->p, g->n, g); });
+  f64tab(R.apYT2, [&](GProb* g) { auto d = stp(g); return item(d.Rt, g->p, d.Y, g->n, d.T2, g->n, g->p, g->n, g->p, g); });
+  f64tab(R.apT2V, [&](GProb* g) { auto d = stp(g); return item(d.Rt, g->p, d.T2, g->n, d.V, g->n, g->p, g->n, g->p, g); });
+  f64tab(R.apT2Y, [&](GProb* g) { auto d = stp(g); return item(d.Rt, g->p, d.T2, g->n, d.Y, g->n, g->p, g->n, g->p, g); });
+  f64tab(R.apYV, [&](GProb* g) { auto d = stp(g); return item(d.Rt, g->p, d.Y, g->n, d.V, g->n, g->p, g->n, g->p, g); });
+  f64tab(R.rrH, [&](GProb* g) { auto d = stp(g); return item(d.V, g->n, d.Y, g->n, d.H, g->p, g->p, g->p, g->n, g); });
+  f64tab(R.rrX, [&](GProb* g) { auto d = stp(g); return item(d.H, g->p, d.V, g->n, d.X, g->n, g->p, g->n, g->p, g); });
+  f64tab(R.rrYx, [&](GProb* g) { auto d = stp(g); return item(d.H, g->p, d.Y, g->n, d.Yx, g->n, g->p, g->n, g->p, g); });
+  if (R.sp != HOTRG_FP64) {
+    const bool split = R.mode == RP_BF16X3;
+    auto op = [&](const Buf* b) { return RpOperand{b[0].p, split ? b[1].p : nullptr}; };
+    std::vector<RpItem> hv, cb, i1, i2, i3;
+    for (GProb* g : R.act) {
+      const long long D = g->D, P = D * D, n = g->n, ldP = pad32(P), ldK2 = pad32(D * D),
+                      ldx = pad32(D), ldn = pad32(n);
+      const int* gate = &g->ctl->active;
+      const OutMap oh = omap2((int)D, D * ldK2, D, (int)D, ldK2, 1);
+      hv.push_back(RpItem{op(g->st->RO[0]), ldP, op(g->st->RO[0]), ldP, g->RA2[0].p,
+                          split ? g->RA2[1].p : nullptr, oh, (int)P, (int)P, (int)ldP, nullptr,
+                          gate});
+      hv.push_back(RpItem{op(g->st->RO[1]), ldP, op(g->st->RO[1]), ldP, g->RA1[0].p,
+                          split ? g->RA1[1].p : nullptr, oh, (int)P, (int)P, (int)ldP, nullptr,
+                          gate});
+      const OutMap om = omap2((int)D, D * n, D, (int)D, n, 1);
+      cb.push_back(RpItem{op(g->RA2), ldK2, op(g->RA1), ldK2, g->M.p, nullptr, om, (int)n, (int)n,
+                          (int)ldK2, nullptr, gate});
+      OutMap o1 = omap2((int)D, D * D * ldP, D, 1, 0, 0);
+      o1.c1 = (int)D;
+      o1.c2 = (int)D;
+      o1.t0 = D * ldP;
+      o1.t1 = ldP;
+      o1.t2 = 1;
+      i1.push_back(RpItem{op(g->RU1), ldx, op(g->st->RO[2]), ldx, g->RX1[0].p,
+                          split ? g->RX1[1].p : nullptr, o1, (int)(D * D), (int)(D * D * D),
+                          (int)ldx, nullptr, gate});
+      const OutMap o2 = omap2((int)D, D * ldn, D, (int)D, ldn, 1);
+      i2.push_back(RpItem{op(g->RX1), ldP, op(g->st->RO[3]), ldP, g->RX2[0].p,
+                          split ? g->RX2[1].p : nullptr, o2, (int)(D * D * D), (int)P, (int)ldP,
+                          nullptr, gate});
+      const OutMap o3 = omap2((int)D, D * D, 1, 1, D, 0);
+      i3.push_back(RpItem{op(g->RX2), ldn, op(g->RU3), ldn, g->Tt.p, nullptr, o3,
+                          (int)(D * D * D), (int)D, (int)ldn, (unsigned long long*)g->scal.p,
+                          gate});
+    }
+    rptab(R.halves, hv, 0);
+    rptab(R.combine, cb, 1);
+    rptab(R.c1, i1, 2);
+    rptab(R.c2, i2, 3);
+    rptab(R.c3, i3, 4);
+  }
+  // the tables are rewritten only when nothing on the stream reads them: a
+  // replay still in flight would index the new, smaller tables with the old
+  // grid sizes
+  HIPCHK(hipStreamSynchronize(c->stream));
+  ensure(c, store, host.size());
+  HIPCHK(hipMemcpyAsync(store.p, host.data(), host.size(), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  char* base = (char*)store.p;
+  R.steps = (GroupStep*)(base + o_steps);
+  R.chol = (CholItem*)(base + o_chol);
+  for (const Pending& pe : pend) {
+    pe.t->items = base + pe.items;
+    for (int cf = 0; cf < 3; ++cf) pe.t->begin[cf] = (int*)(base + pe.begin[cf]);
+  }
+  R.pmax = 16;
+  R.max_pn = 1;
+  for (GProb* g : R.act) {
+    R.pmax = std::max(R.pmax, g->p);
+    R.max_pn = std::max(R.max_pn, (long long)g->p * g->n);
+  }
+}
+
+}  // namespace
+
+namespace {
+
+// Step (1-based) from which a problem's steps keep the same dims and the same
+// contraction precision, or n_steps + 1 if that never happens within the run.
+int steady_step(const hotrg_opts& o, int prec, int dx, int dy, int first_reduced) {
+  for (int k = 1; k <= o.n_steps; ++k) {
+    const int dn = (int)std::min<long long>(o.d_cut, (long long)dx * dx);
+    // dims (D, D, D) repeat from here on; a reduced precision also has to have
+    // started (steps before first_reduced are FP64)
+    if (dx == dy && dy == dn && (prec == HOTRG_FP64 || k >= first_reduced)) return k;
+    const int ndx = dy;
+    dy = dn;
+    dx = ndx;
+  }
+  return o.n_steps + 1;
+}
+
+void free_group_buffers(hotrg_ctx* c, GProb& g) {
+  Buf* bs[] = {&g.M, &g.eig, &g.U, &g.scal, &g.Tt, &g.U1, &g.U3};
+  for (Buf* b : bs) ctx_free(c, *b);
+  for (Buf* arr : {g.RA1, g.RA2, g.RX1, g.RX2, g.RU1, g.RU3})
+    for (int h = 0; h < 2; ++h) ctx_free(c, arr[h]);
+}
+
+// ln Z / N and the per-step records of a finished state into res.
+void finish_into(hotrg_ctx* c, hotrg_state* st, const GProb& g, hotrg_result* res, double secs) {
+  double lnz = 0;
+  hotrg_status fs = hotrg_finish(c, st, &lnz);
+  if (fs != HOTRG_OK) fail(fs, g_err);
+  const int K = g.o.n_steps;
+  if (res->steps || res->spectra) {
+    fetch_info(c, st, 0, K, nullptr, res->steps, res->spectra);
+    if (res->steps)
+      for (int k = 0; k < K; ++k) {
+        res->steps[k].dx = g.dxs[k];
+        res->steps[k].dy = g.dys[k];
+        res->steps[k].d_new = g.dns[k];
+      }
+  }
+  res->lnz_per_site = lnz;
+  res->n_steps = K;
+  res->prec_used = g.o.prec;
+  res->err_bound = st->err_bound;
+  res->seconds = secs;
+}
+
+void run_grouped_impl(hotrg_ctx* c, int N, const hotrg_model_params* params,
+                      const hotrg_opts* opts, hotrg_result* results, hotrg_status* statuses) {
+  HIPCHK(hipSetDevice(c->device));
+  const auto t0 = std::chrono::steady_clock::now();
+  auto secs = [&] {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  };
+  const bool timing = c->timing;
+  c->timing = false;
+  std::vector<GProb> P(N);
+  std::vector<char> done(N, 0);
+  // plan: the steady step of each problem and whether the batch takes it
+  int group_sp = -1;
+  for (int i = 0; i < N; ++i) {
+    GProb& g = P[i];
+    g.idx = i;
+    statuses[i] = guard([&] {
+      check_opts(&opts[i]);
+      int dx = 0, dy = 0;
+      (void)build_tensor(&params[i], &dx, &dy);
+      g.o = resolve_prec(&opts[i], dx, dy);
+      check_opts(&g.o);
+      const int fr = first_reduced_step(g.o.prec, g.o.tol);
+      const int ks = steady_step(g.o, g.o.prec, dx, dy, fr);
+      // dims of every step
+      int x = dx, y = dy;
+      for (int k = 1; k <= g.o.n_steps; ++k) {
+        const int dn = (int)std::min<long long>(g.o.d_cut, (long long)x * x);
+        g.dxs.push_back(x);
+        g.dys.push_back(y);
+        g.dns.push_back(dn);
+        if (k == ks) {
+          g.D = x;
+          g.sp = step_is_reduced(g.o.prec, k, x, y, g.o.d_cut, fr) ? g.o.prec : HOTRG_FP64;
+        }
+        const int nx = y;
+        y = dn;
+        x = nx;
+      }
+      // (a reduced-precision problem steady from step 1 would start from FP64
+      // operands: it runs alone)
+      bool ok = ks <= g.o.n_steps && g.o.isometry == HOTRG_ISO_ONE_SIDED &&
+                g.o.eig == HOTRG_EIG_AUTO && !(ks == 1 && g.sp != HOTRG_FP64);
+      if (ok) {
+        g.n = g.D * g.D;
+        g.need = std::max(g.D + 1, std::min(g.o.spec_len, g.n));
+        g.p = (std::min(128, std::max(2 * g.D, g.need + 16)) + 15) / 16 * 16;
+        ok = g.need + 16 <= g.p && g.p <= 128 && 4 * g.p <= g.n;
+      }
+      if (ok && group_sp < 0) group_sp = g.sp;
+      g.k_host = ok && g.sp == group_sp ? ks - 1 : -1;  // -1: runs alone
+    });
+  }
+  // warm-up steps one problem at a time; problems outside the batch run whole
+  for (int i = 0; i < N; ++i) {
+    GProb& g = P[i];
+    if (statuses[i] != HOTRG_OK) {
+      done[i] = 1;
+      continue;
+    }
+    statuses[i] = guard([&] {
+      int dx = 0, dy = 0;
+      std::vector<double> T0 = build_tensor(&params[i], &dx, &dy);
+      g.st = new_state(c, T0, dx, dy, g.o.prec);
+      g.st->first_reduced = first_reduced_step(g.o.prec, g.o.tol);
+      const int upto = g.k_host >= 0 ? g.k_host : g.o.n_steps;
+      while (g.st->k < upto) do_step(c, g.st, &g.o);
+      if (g.k_host < 0) {
+        finish_into(c, g.st, g, &results[i], secs());
+        done[i] = 1;
+      }
+    });
+    if (statuses[i] != HOTRG_OK) done[i] = 1;
+  }
+  // per-problem buffers of the batch
+  std::vector<GProb*> grp;
+  for (int i = 0; i < N; ++i)
+    if (!done[i]) grp.push_back(&P[i]);
+  Buf ctlbuf, tables;
+  hipGraphExec_t exec = nullptr;
+  try {
+    if (!grp.empty()) {
+      const bool red = group_sp != HOTRG_FP64;
+      const int mode = red ? rp_mode(group_sp) : RP_F32;
+      const size_t es = mode == RP_F32 ? 4 : 2;
+      const int halves = red && mode == RP_BF16X3 ? 2 : 1;
+      ensure(c, ctlbuf, grp.size() * sizeof(GroupCtl));
+      std::vector<GroupCtl> ctl(grp.size());
+      for (size_t j = 0; j < grp.size(); ++j) {
+        GProb& g = *grp[j];
+        g.ctl = (GroupCtl*)ctlbuf.p + j;
+        ctl[j] = GroupCtl{1, 0, 0, g.st->k};
+        reserve_records(c, g.st, g.o.n_steps, g.o.spec_len);
+        const long long D = g.D, n = g.n, pn = (long long)g.p * n, pp = (long long)g.p * g.p;
+        ensure(c, g.M, (size_t)(n * n) * 8);
+        ensure(c, g.eig, (size_t)(5 * pn + 3 * pp + 2 * g.p + 16) * 8);
+        ensure(c, g.U, (size_t)(n * D) * 8);
+        ensure(c, g.scal, 64);
+        if (red) {
+          const long long ldP = pad32(D * D), ldx = pad32(D), ldn = pad32(n);
+          ensure(c, g.Tt, (size_t)(D * D * D * D) * 4);
+          for (int h = 0; h < halves; ++h) {
+            ensure(c, g.RA1[h], (size_t)(n * ldP) * es);
+            ensure(c, g.RA2[h], (size_t)(n * ldP) * es);
+            ensure(c, g.RX1[h], (size_t)(D * D * D * ldP) * es);
+            ensure(c, g.RX2[h], (size_t)(D * D * D * ldn) * es);
+            ensure(c, g.RU1[h], (size_t)(D * D * ldx) * es);
+            ensure(c, g.RU3[h], (size_t)(D * ldn) * es);
+            // zero padding past the true K stays zero: the products write
+            // only the valid columns
+            Buf* pads[] = {&g.RA1[h], &g.RA2[h], &g.RX1[h], &g.RX2[h], &g.RU1[h], &g.RU3[h]};
+            for (Buf* b : pads) HIPCHK(hipMemsetAsync(b->p, 0, b->bytes, c->stream));
+          }
+        } else {
+          ensure(c, g.Tt, (size_t)(D * D * D * D) * 8);
+          ensure(c, g.U1, (size_t)(n * D) * 8);
+          ensure(c, g.U3, (size_t)(n * D) * 8);
+        }
+      }
+      if (!red) {
+        // FP64 contractions run problem after problem through the context's
+        // intermediates: sized for the largest
+        long long xmax = 1;
+        for (GProb* g : grp) xmax = std::max(xmax, (long long)g->D * g->D * g->D * g->D * g->D);
+        ensure(c, c->X1, (size_t)xmax * 8);
+        ensure(c, c->X2, (size_t)xmax * 8);
+      }
+      HIPCHK(hipMemcpyAsync(ctlbuf.p, ctl.data(), ctl.size() * sizeof(GroupCtl),
+                            hipMemcpyHostToDevice, c->stream));
+      HIPCHK(hipStreamSynchronize(c->stream));
+      GRun R;
+      R.sp = group_sp;
+      R.mode = mode;
+      std::vector<GProb*> cur;
+      bool eager_done = false;
+      for (;;) {
+        std::vector<GProb*> act;
+        for (GProb* g : grp)
+          if (g->k_host < g->o.n_steps) act.push_back(g);
+        if (act.empty()) break;
+        if (act != cur) {
+          // replays of the previous graph finish before its tables change
+          HIPCHK(hipStreamSynchronize(c->stream));
+          if (exec) {
+            (void)hipGraphExecDestroy(exec);
+            exec = nullptr;
+          }
+          std::vector<std::vector<long long>> keys;
+          R.act = act;
+          R.cfg[0] = R.cfg[1] = R.cfg[2] = R.cfg[3] = R.cfg[4] = -1;
+          group_tables(c, R, tables, &keys);
+          bool untuned = false;
+          {
+            std::lock_guard<std::mutex> lk(g_gtune_mu);
+            for (size_t q = 0; q < keys.size(); ++q) {
+              auto it = g_gtune.find(keys[q]);
+              if (it != g_gtune.end()) R.cfg[q] = it->second;
+              else untuned = true;
+            }
+          }
+          if (!eager_done || untuned) {
+            // an eager sweep: tunes the shapes, allocates what the step needs
+            group_sweep(c, R, true, &keys);
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipStreamSynchronize(c->stream));
+            eager_done = true;
+            ++c->g_sweeps;
+            for (GProb* g : act) ++g->k_host;
+            cur.clear();
+            continue;
+          }
+          hipGraph_t graph = nullptr;
+          HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+          try {
+            group_sweep(c, R, false, &keys);
+          } catch (...) {
+            (void)hipStreamEndCapture(c->stream, &graph);
+            if (graph) (void)hipGraphDestroy(graph);
+            throw;
+          }
+          HIPCHK(hipStreamEndCapture(c->stream, &graph));
+          const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+          (void)hipGraphDestroy(graph);
+          HIPCHK(ie);
+          ++c->g_captures;
+          cur = act;
+        }
+        HIPCHK(hipGraphLaunch(exec, c->stream));
+        ++c->g_sweeps;
+        ++c->g_replays;
+        for (GProb* g : act) ++g->k_host;
+      }
+      HIPCHK(hipStreamSynchronize(c->stream));
+      HIPCHK(hipMemcpy(ctl.data(), ctlbuf.p, ctl.size() * sizeof(GroupCtl), hipMemcpyDeviceToHost));
+      for (size_t j = 0; j < grp.size(); ++j) {
+        GProb& g = *grp[j];
+        const int i = g.idx;
+        if (ctl[j].fail || ctl[j].k != g.o.n_steps) {
+          // the batched eigensolve did not converge within its budget: this
+          // problem is run again alone (with the dense fallback)
+          ++c->g_fallbacks;
+          hotrg_state_free(c, g.st);
+          g.st = nullptr;
+          statuses[i] = run_problem(c, &params[i], &g.o, &results[i], nullptr);
+          continue;
+        }
+        statuses[i] = guard([&] {
+          for (int k = g.st->k + 1; k <= g.o.n_steps; ++k)
+            if (group_sp != HOTRG_FP64) g.st->err_bound += kErrPerStep[group_sp] * std::ldexp(1.0, -k);
+          g.st->k = g.o.n_steps;
+          finish_into(c, g.st, g, &results[i], secs());
+        });
+      }
+    }
+  } catch (...) {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    for (GProb& g : P) {
+      free_group_buffers(c, g);
+      if (g.st) hotrg_state_free(c, g.st);
+    }
+    ctx_free(c, ctlbuf);
+    ctx_free(c, tables);
+    c->timing = timing;
+    throw;
+  }
+  if (exec) (void)hipGraphExecDestroy(exec);
+  for (GProb& g : P) {
+    free_group_buffers(c, g);
+    if (g.st) hotrg_state_free(c, g.st);
+  }
+  ctx_free(c, ctlbuf);
+  ctx_free(c, tables);
+  c->timing = timing;
 }
 
 }  // namespace
@@ -1033,6 +1718,37 @@ hotrg_status hotrg_plan(const hotrg_model_params* params, const hotrg_opts* o, i
     if (prec) *prec = pl.err_bound > 0.0 ? r.prec : HOTRG_FP64;
     if (first_reduced) *first_reduced = pl.first_reduced;
     if (err_bound) *err_bound = pl.err_bound;
+  });
+}
+
+hotrg_status hotrg_run_grouped(hotrg_ctx* c, int n, const hotrg_model_params* params,
+                               const hotrg_opts* opts, hotrg_result* results,
+                               hotrg_status* statuses) {
+  std::vector<hotrg_status> st(n > 0 ? n : 0, HOTRG_OK);
+  hotrg_status s = guard([&] {
+    if (!c || n < 0 || (n > 0 && (!params || !opts || !results)))
+      fail(HOTRG_ERR_INVALID, "NULL argument");
+    run_grouped_impl(c, n, params, opts, results, st.data());
+  });
+  if (s != HOTRG_OK) {
+    for (auto& x : st) x = s;
+  }
+  hotrg_status first = HOTRG_OK;
+  for (int i = 0; i < n; ++i) {
+    if (statuses) statuses[i] = st[i];
+    if (st[i] != HOTRG_OK && first == HOTRG_OK) first = st[i];
+  }
+  return s != HOTRG_OK ? s : first;
+}
+
+hotrg_status hotrg_ctx_group_stats(hotrg_ctx* c, uint64_t* sweeps, uint64_t* replays,
+                                   uint64_t* captures, uint64_t* fallbacks) {
+  return guard([&] {
+    if (!c) fail(HOTRG_ERR_INVALID, "ctx is NULL");
+    if (sweeps) *sweeps = c->g_sweeps;
+    if (replays) *replays = c->g_replays;
+    if (captures) *captures = c->g_captures;
+    if (fallbacks) *fallbacks = c->g_fallbacks;
   });
 }
 

@@ -54,21 +54,11 @@ __device__ __forceinline__ double wave_max(double v) {
 // go global -> registers -> LDS; the next slab's global loads are issued
 // before the current slab's MFMAs so that they overlap.
 template <int BM, int BN, int BK, int BL>
-__global__ __launch_bounds__(256) void k_gemm_f64(const double* __restrict__ A, long long lda,
-                                                  const double* __restrict__ B, long long ldb,
-                                                  double* __restrict__ C, OutMap om, int M, int N,
-                                                  int K, unsigned long long* maxbits, int kchunk,
-                                                  long long cstride) {
+__device__ __forceinline__ void f64_tile(const double* __restrict__ A, long long lda,
+                                         const double* __restrict__ B, long long ldb,
+                                         double* __restrict__ C, const OutMap& om, int M, int N,
+                                         int K, unsigned long long* maxbits, int m0, int n0) {
   constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 16, TN = WN / 16;
-  // split-K: block z sums k in [z*kchunk, min((z+1)*kchunk, K)) into C + z*cstride
-  if (kchunk > 0) {
-    const int z = blockIdx.z;
-    const int kb = z * kchunk;
-    A += kb;
-    B += BL == B_NCONTIG ? (long long)kb * ldb : kb;
-    C += z * cstride;
-    K = K - kb < kchunk ? K - kb : kchunk;
-  }
   constexpr int A_PER = BM * BK / 256, B_PER = BN * BK / 256;
   static_assert(BM * BK % 256 == 0 && BN * BK % 256 == 0, "tile must split over 256 threads");
   __shared__ double As[BM][BK + 1];
@@ -79,7 +69,6 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const double* __restrict__ A, 
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
 
   d4 acc[TM][TN];
 #pragma unroll
@@ -181,6 +170,59 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const double* __restrict__ A, 
     mx = wave_max(mx);
     if (lane == 0) atomic_max_bits(maxbits, mx);
   }
+}
+
+template <int BM, int BN, int BK, int BL>
+__global__ __launch_bounds__(256) void k_gemm_f64(const double* __restrict__ A, long long lda,
+                                                  const double* __restrict__ B, long long ldb,
+                                                  double* __restrict__ C, OutMap om, int M, int N,
+                                                  int K, unsigned long long* maxbits, int kchunk,
+                                                  long long cstride) {
+  // split-K: block z sums k in [z*kchunk, min((z+1)*kchunk, K)) into C + z*cstride
+  if (kchunk > 0) {
+    const int z = blockIdx.z;
+    const int kb = z * kchunk;
+    A += kb;
+    B += BL == B_NCONTIG ? (long long)kb * ldb : kb;
+    C += z * cstride;
+    K = K - kb < kchunk ? K - kb : kchunk;
+  }
+  f64_tile<BM, BN, BK, BL>(A, lda, B, ldb, C, om, M, N, K, maxbits, blockIdx.y * BM,
+                           blockIdx.x * BN);
+}
+
+// Grouped form over a device table of products (the block eigensolver of a
+// batch of problems): workgroup b takes tile b - begin[i] of the item i whose
+// range holds b; an item whose gate reads 0 skips its tiles.
+template <int BM, int BN, int BK, int BL>
+__global__ __launch_bounds__(256) void k_gemm_f64_grouped(const F64Item* __restrict__ items,
+                                                          const int* __restrict__ begin,
+                                                          int count) {
+  int lo = 0, hi = count - 1;
+  const int b = blockIdx.x;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (begin[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  const F64Item& it = items[lo];
+  if (it.gate && *it.gate == 0) return;
+  const int local = b - begin[lo];
+  const int tn = (it.N + BN - 1) / BN;
+  f64_tile<BM, BN, BK, BL>(it.A, it.lda, it.B, it.ldb, it.C, out_rowmajor(it.ldc), it.M, it.N,
+                           it.K, nullptr, (local / tn) * BM, (local % tn) * BN);
+}
+
+int f64_group_tiles(const F64Item& it) { return ((it.M + 63) / 64) * ((it.N + 63) / 64); }
+
+void gemm_f64_grouped(int blayout, const F64Item* d_items, const int* d_begin, int count,
+                      int tiles, hipStream_t s) {
+  if (count <= 0 || tiles <= 0) return;
+  if (blayout == B_NCONTIG)
+    hipLaunchKernelGGL((k_gemm_f64_grouped<64, 64, 16, B_NCONTIG>), dim3(tiles), dim3(256), 0, s,
+                       d_items, d_begin, count);
+  else
+    hipLaunchKernelGGL((k_gemm_f64_grouped<64, 64, 16, B_KCONTIG>), dim3(tiles), dim3(256), 0, s,
+                       d_items, d_begin, count);
 }
 
 // Large-GEMM variant: 128 x 128 block tile, K slab BK = 32, LDS double

@@ -85,14 +85,15 @@ __device__ __forceinline__ void rp_load(const void* __restrict__ hi, const void*
 
 // Block tile 256 x BN with 8 waves; each wave owns 16 TM rows x 64 columns
 // (TM MFMA tiles of 16 rows): TM = 4 for BN = 128, TM = 8 for BN = 256.
-template <int MODE, int OUT, int TAG, int TM, int BN, int NST>
-__global__ __launch_bounds__(512) void k_gemm_rp(const void* __restrict__ Ahi,
-                                                 const void* __restrict__ Alo, long long lda,
-                                                 const void* __restrict__ Bhi,
-                                                 const void* __restrict__ Blo, long long ldb,
-                                                 void* __restrict__ C, void* __restrict__ Clo,
-                                                 OutMap om, int M, int N, int K,
-                                                 unsigned long long* maxbits) {
+// One output tile at rows m0.., columns n0.. (shared by the single-product
+// kernel and the grouped one).
+template <int MODE, int OUT, int TM, int BN, int NST>
+__device__ __forceinline__ void rp_tile(const void* __restrict__ Ahi, const void* __restrict__ Alo,
+                                        long long lda, const void* __restrict__ Bhi,
+                                        const void* __restrict__ Blo, long long ldb,
+                                        void* __restrict__ C, void* __restrict__ Clo,
+                                        const OutMap& om, int M, int N, int K,
+                                        unsigned long long* maxbits, int m0, int n0) {
   constexpr int BM = 256, A_BYTES = BM * 128, B_BYTES = BN * 128;
   constexpr int STAGE = A_BYTES + B_BYTES;
   constexpr int WN = BN / 64;               // waves along N
@@ -102,7 +103,6 @@ __global__ __launch_bounds__(512) void k_gemm_rp(const void* __restrict__ Ahi,
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
   const int li = lane & 15, lg = lane >> 4;
 
   f4 acc[TM][4];
@@ -321,6 +321,45 @@ __global__ __launch_bounds__(512) void k_gemm_rp(const void* __restrict__ Ahi,
   }
 }
 
+template <int MODE, int OUT, int TAG, int TM, int BN, int NST>
+__global__ __launch_bounds__(512) void k_gemm_rp(const void* __restrict__ Ahi,
+                                                 const void* __restrict__ Alo, long long lda,
+                                                 const void* __restrict__ Bhi,
+                                                 const void* __restrict__ Blo, long long ldb,
+                                                 void* __restrict__ C, void* __restrict__ Clo,
+                                                 OutMap om, int M, int N, int K,
+                                                 unsigned long long* maxbits) {
+  rp_tile<MODE, OUT, TM, BN, NST>(Ahi, Alo, lda, Bhi, Blo, ldb, C, Clo, om, M, N, K, maxbits,
+                                  blockIdx.y * 256, blockIdx.x * BN);
+}
+
+// Grouped form: one launch over the output tiles of every product in the
+// table (problems of a batch with uneven shapes); workgroup b takes tile
+// b - tile_begin of the item whose range holds b.  Items with a gate that
+// reads 0 (a finished problem) skip their tiles.
+__device__ __forceinline__ int find_item(const int* __restrict__ begin, int count, int b) {
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {  // last item with begin <= b
+    const int mid = (lo + hi + 1) >> 1;
+    if (begin[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <int MODE, int OUT, int TM, int BN, int NST>
+__global__ __launch_bounds__(512) void k_gemm_rp_grouped(const RpItem* __restrict__ items,
+                                                         const int* __restrict__ begin,
+                                                         int count) {
+  const int g = find_item(begin, count, blockIdx.x);
+  const RpItem& it = items[g];
+  if (it.gate && *it.gate == 0) return;
+  const int local = blockIdx.x - begin[g];
+  const int tn = (it.N + BN - 1) / BN;
+  rp_tile<MODE, OUT, TM, BN, NST>(it.A.hi, it.A.lo, it.lda, it.B.hi, it.B.lo, it.ldb, it.C,
+                                  it.Clo, it.om, it.M, it.N, it.K, it.maxbits,
+                                  (local / tn) * 256, (local % tn) * BN);
+}
+
 // tile configuration: 0 = 256 x 256 blocks, two stages (N >= 256);
 // 1 = 256 x 128 blocks, two stages; 2 = 256 x 128 blocks, three stages
 static int rp_config(int N) {
@@ -399,6 +438,53 @@ static void launch_rp_tag(int tag, const RpOperand& A, long long lda, const RpOp
     }
   }
   launch_rp_cfg<MODE, OUT>(rp_config(N), tag, A, lda, B, ldb, C, Clo, om, M, N, K, maxbits, s);
+}
+
+// ---- grouped launch ----
+int rp_group_tiles(const RpItem& it, int cfg) {
+  const int bn = cfg == 0 ? 256 : 128;
+  return ((it.M + 255) / 256) * ((it.N + bn - 1) / bn);
+}
+
+template <int MODE, int OUT, int TM, int BN, int NST>
+static void launch_rp_grouped_shape(const RpItem* d_items, const int* d_begin, int count,
+                                    int tiles, hipStream_t s) {
+  constexpr int LDS = NST * (256 + BN) * 128;
+  auto kern = k_gemm_rp_grouped<MODE, OUT, TM, BN, NST>;
+  static const bool ok = hipFuncSetAttribute((const void*)kern,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             LDS) == hipSuccess;
+  (void)ok;
+  hipLaunchKernelGGL(kern, dim3(tiles), dim3(512), LDS, s, d_items, d_begin, count);
+}
+
+template <int MODE, int OUT>
+static void launch_rp_grouped_cfg(int cfg, const RpItem* d_items, const int* d_begin, int count,
+                                  int tiles, hipStream_t s) {
+  if (cfg == 0)
+    launch_rp_grouped_shape<MODE, OUT, 8, 256, 2>(d_items, d_begin, count, tiles, s);
+  else if (cfg == 2)
+    launch_rp_grouped_shape<MODE, OUT, 4, 128, 3>(d_items, d_begin, count, tiles, s);
+  else
+    launch_rp_grouped_shape<MODE, OUT, 4, 128, 2>(d_items, d_begin, count, tiles, s);
+}
+
+void gemm_rp_grouped(int mode, int out, int cfg, const RpItem* d_items, const int* d_begin,
+                     int count, int tiles, hipStream_t s) {
+  if (count <= 0 || tiles <= 0) return;
+  if (mode == RP_F32) {
+    if (out == RP_OUT_F32)
+      launch_rp_grouped_cfg<RP_F32, RP_OUT_F32>(cfg, d_items, d_begin, count, tiles, s);
+    else
+      launch_rp_grouped_cfg<RP_F32, RP_OUT_F64>(cfg, d_items, d_begin, count, tiles, s);
+  } else {
+    if (out == RP_OUT_SPLIT)
+      launch_rp_grouped_cfg<RP_BF16X3, RP_OUT_SPLIT>(cfg, d_items, d_begin, count, tiles, s);
+    else if (out == RP_OUT_F64)
+      launch_rp_grouped_cfg<RP_BF16X3, RP_OUT_F64>(cfg, d_items, d_begin, count, tiles, s);
+    else
+      launch_rp_grouped_cfg<RP_BF16X3, RP_OUT_F32>(cfg, d_items, d_begin, count, tiles, s);
+  }
 }
 
 bool gemm_rp(int mode, const RpOperand& A, long long lda, const RpOperand& B, long long ldb,

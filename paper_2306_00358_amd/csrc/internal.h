@@ -26,7 +26,8 @@ struct OutMap {
 };
 
 // Two-level map: m = mh * rr + ml -> mh*sh + ml*sl; n = nh * cr + nl -> nh*th + nl*tl.
-inline OutMap omap2(int rr, long long sh, long long sl, int cr, long long th, long long tl) {
+__host__ __device__ inline OutMap omap2(int rr, long long sh, long long sl, int cr, long long th,
+                                        long long tl) {
   OutMap o;
   o.r1 = 1; o.r2 = rr; o.s0 = sh; o.s1 = 0; o.s2 = sl;
   o.c1 = 1; o.c2 = cr; o.t0 = th; o.t1 = 0; o.t2 = tl;
@@ -34,7 +35,7 @@ inline OutMap omap2(int rr, long long sh, long long sl, int cr, long long th, lo
 }
 
 // Plain row-major output of an M x N matrix with leading dimension ld.
-inline OutMap out_rowmajor(long long ld) { return omap2(1, ld, 0, 1, 1, 0); }
+__host__ __device__ inline OutMap out_rowmajor(long long ld) { return omap2(1, ld, 0, 1, 1, 0); }
 
 enum BLayout { B_NCONTIG = 0, B_KCONTIG = 1 };
 
@@ -49,6 +50,22 @@ enum GemmTag { GEMM_TAG_OTHER = 0, GEMM_TAG_ENV = 1, GEMM_TAG_C2 = 2, GEMM_NO_TU
 void gemm_f64(const double* A, long long lda, const double* B, long long ldb, int blayout,
               double* C, const OutMap& om, int M, int N, int K,
               unsigned long long* maxbits, hipStream_t s, int tag = GEMM_TAG_OTHER);
+
+// One product of a grouped FP64 launch (device table): C (row-major, leading
+// dimension ldc) = A B with B's layout given per launch; gate as for RpItem.
+struct F64Item {
+  const double* A;
+  long long lda;
+  const double* B;
+  long long ldb;
+  double* C;
+  long long ldc;
+  int M, N, K;
+  const int* gate;
+};
+int f64_group_tiles(const F64Item& it);  // 64 x 64 output tiles
+void gemm_f64_grouped(int blayout, const F64Item* d_items, const int* d_begin, int count,
+                      int tiles, hipStream_t s);
 
 // Split-K FP64 GEMM for products with small M x N and long K: partial
 // products of K chunks go to `partials` (ceil(K/kchunk) * M * N doubles) and
@@ -91,6 +108,29 @@ bool gemm_rp(int mode, const RpOperand& A, long long lda, const RpOperand& B, lo
              int out, void* C, void* Clo, const OutMap& om, int M, int N, int K,
              unsigned long long* maxbits, hipStream_t s, int tag);
 inline long long pad32(long long k) { return (k + 31) / 32 * 32; }
+
+// One product of a grouped launch (device table): the operands and output
+// of gemm_rp, and a gate (device int, may be null) that skips the product's
+// tiles while it reads 0.
+struct RpItem {
+  RpOperand A;
+  long long lda;
+  RpOperand B;
+  long long ldb;
+  void* C;
+  void* Clo;
+  OutMap om;
+  int M, N, K;
+  unsigned long long* maxbits;
+  const int* gate;
+};
+// Output tiles of an item under tile configuration cfg (0: 256 x 256,
+// 1: 256 x 128 two stages, 2: 256 x 128 three stages).
+int rp_group_tiles(const RpItem& it, int cfg);
+// One launch over `tiles` tiles; d_begin[i] is the first tile of item i
+// (ascending, d_begin[0] = 0).  Requirements per item as for gemm_rp.
+void gemm_rp_grouped(int mode, int out, int cfg, const RpItem* d_items, const int* d_begin,
+                     int count, int tiles, hipStream_t s);
 
 // Reduced-precision operands of a step from the coarse tensor `src` (f64 or
 // f32, legs optionally transposed, divided by the max read from maxbits).
@@ -136,6 +176,21 @@ void launch_isometry(const double* V, int cols, int n, int dn, const int* kept, 
                      hipStream_t s);
 void launch_trace(const double* M, int n, double* out, hipStream_t s);
 size_t topk_workspace_doubles(int n, int p);
+// Batched shifted Cholesky-QR step of the block eigensolver: per problem,
+// Rt = (R^-1)^T with G (+ shift) = R^T R (one workgroup each; p <= 128, a
+// multiple of 16).  Pass 0 and 1 factor the diagonally scaled, shifted G,
+// pass 2 the plain one; pass 1 between checks (!full) is skipped when G is
+// the identity to 1e-2.  A non-positive pivot sets *fail.
+struct CholItem {
+  const double* G;
+  double* Rt;
+  int* fail;
+  const int* gate;
+  int p;
+  double shift_rel;
+};
+void launch_chol_inv_batched(const CholItem* d_items, int count, int pmax, int pass, bool full,
+                             hipStream_t s);
 bool topk_eigs(rocblas_handle blas, const double* M, int n, int p, int need, double tol,
                int q_first, double* ws, double* W, double* Xout, int* dinfo, int* iters,
                int* enough, double* resid, hipStream_t s);
@@ -147,6 +202,43 @@ void launch_finish(const void* Tn, bool f32, int dx, int dy, double weight, cons
                    double* out, hipStream_t s);
 void launch_f64_to_f32(const double* x, float* y, long long n, hipStream_t s);
 void launch_f32_to_f64(const float* x, double* y, long long n, hipStream_t s);
+
+// ---- lockstep batch engine (group.hip) ----
+constexpr int kGroupRec = 6;  // doubles per step record (as the engine's)
+// Per-problem control block, updated by the kernels of a sweep.
+struct GroupCtl {
+  int active;  // the problem has steps left
+  int iter;    // its block eigensolver is still iterating in this step
+  int fail;    // sticky: eigensolver budget exhausted or a Cholesky pivot <= 0
+  int k;       // steps done
+};
+// Per-problem descriptor of a run (device memory, fixed while it runs).
+struct GroupStep {
+  GroupCtl* ctl;
+  int n, dn, dy, p, need, trunc, spec_len, K;
+  double tau, tol;
+  double* trace;
+  double* W;
+  double* X;
+  int* kept;
+  double *V, *Y, *T2, *Yx, *G, *Rt, *H, *res;
+  double* recs;
+  double* spec;
+  double* acc;
+  const void* Tt;
+  int tt_f32;
+  unsigned long long* maxbits;
+};
+void group_begin(const GroupStep* d, int count, hipStream_t s);
+void group_seed(const GroupStep* d, int count, long long max_pn, hipStream_t s);
+void group_symm_h(const GroupStep* d, int count, hipStream_t s);
+void group_jacobi(const GroupStep* d, int count, int pmax, hipStream_t s);
+void group_resid(const GroupStep* d, int count, bool last, hipStream_t s);
+void group_restart(const GroupStep* d, int count, long long max_pn, hipStream_t s);
+void group_spectrum(const GroupStep* d, int count, hipStream_t s);
+void group_norm(const GroupStep* d, int count, hipStream_t s);
+void group_zero_max(const GroupStep* d, int count, hipStream_t s);
+void group_advance(const GroupStep* d, int count, hipStream_t s);
 
 // ---- engine hooks used by the scheduler (sched.cpp) ----
 // C1 -> C2 -> C3 in FP64 on caller buffers (X1, X2: dn*dx*dy*dx*dy doubles;

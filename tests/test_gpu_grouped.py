@@ -1,0 +1,115 @@
+"""Lockstep batches (hotrg_run_grouped): grouped launches over uneven problems,
+the batched block eigensolver with Jacobi Rayleigh-Ritz, one HIP graph per
+sweep.  FP64 results against the oracle (ln Z/N at 1e-12, per-step spectra
+at the conditioning tolerance of tests/sensitivity.py); every result against
+the same problem run alone; replays of the captured sweep actually used."""
+
+import json
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import hotrg, tensors
+from tests.test_gpu_parity import _compare_run
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+BETA_C = math.log(1 + math.sqrt(2)) / 2
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a GPU")
+    return torch
+
+
+def test_grouped_ising_d32_vs_stored_oracle(torch_cuda):
+    # the three D_cut = 32 temperatures in one batch, against the stored oracle
+    from paper_2306_00358_amd import Context, hotrg_run_grouped, make_opts, model_params
+
+    with open(os.path.join(GOLDEN, "ising_d32.json")) as f:
+        runs = json.load(f)["runs"]
+    params = [model_params("ising", beta=r["beta"]) for r in runs]
+    opts = [make_opts(32, 30, spec_len=33) for _ in runs]
+    with Context(0) as ctx:
+        got, st = hotrg_run_grouped(ctx, params, opts, with_steps=True)
+        stats = ctx.group_stats()
+    say("group stats", stats)
+    assert st == [0] * len(runs)
+    # steady from step 7 (dims 32, 32, 32): one eager sweep, then replays
+    assert stats["replays"] >= 30 - 7 - 1 and stats["fallbacks"] == 0
+    for r, g in zip(runs, got):
+        say("T", 1 / r["beta"])
+        # ln Z/N and torus estimates at 1e-12, dims and kept counts exactly,
+        # spectra and truncation errors at the per-step conditioning tolerance
+        _compare_run(g, r["lnz_per_site"], r["steps"], r["spectra"], drift=r["spectra_drift"])
+
+
+def _mixed_batch():
+    from paper_2306_00358_amd import make_opts, model_params
+
+    P, O = [], []
+    # uneven D_cut and step counts (the active set shrinks: the sweep is
+    # captured again), XY and Ising, FP64; one FP32 problem and one two-sided
+    # problem, which the batch runs alone
+    for i, (model, beta, n_max, d_cut, K) in enumerate([
+            ("xy", 0.85, 3, 24, 16), ("ising", BETA_C, 0, 32, 20), ("xy", 1.25, 4, 32, 12),
+            ("ising", 0.5, 0, 16, 24), ("xy", 1.05, 2, 16, 18), ("ising", 0.41, 0, 24, 14)]):
+        P.append(model_params(model, beta=beta, n_max=n_max))
+        kw = dict(trunc="multiplet", degen_tol=1e-5) if model == "xy" else {}
+        O.append(make_opts(d_cut, K, spec_len=4, **kw))
+    P.append(model_params("ising", beta=0.45))
+    O.append(make_opts(16, 12, prec="fp32"))
+    P.append(model_params("ising", beta=0.46))
+    O.append(make_opts(8, 12, isometry="two"))
+    return P, O
+
+
+def test_grouped_equals_alone_and_oracle(torch_cuda):
+    from paper_2306_00358_amd import Context, hotrg_run, hotrg_run_grouped
+
+    P, O = _mixed_batch()
+    with Context(0) as ctx:
+        got, st = hotrg_run_grouped(ctx, P, O)
+        stats = ctx.group_stats()
+        alone = [hotrg_run(ctx, p, o) for p, o in zip(P, O)]
+    say("group stats", stats)
+    assert st == [0] * len(P)
+    assert stats["captures"] >= 2 and stats["fallbacks"] == 0
+    for p, o, g, a in zip(P, O, got, alone):
+        rel = abs(g["lnz_per_site"] - a["lnz_per_site"]) / abs(a["lnz_per_site"])
+        say("model", p.model, "d_cut", o.d_cut, "K", o.n_steps, "prec", o.prec, "vs alone", rel)
+        assert rel <= (1e-12 if o.prec == 0 else 2.0 * a["err_bound"])
+        if o.prec == 0 and o.isometry == 0:
+            T0 = tensors.ising(p.beta) if p.model == 0 else tensors.xy(p.beta, p.n_max)
+            want = hotrg.run(T0, o.d_cut, o.n_steps, "multiplet" if o.trunc else "plain",
+                             o.degen_tol).lnz_per_site
+            assert abs(g["lnz_per_site"] - want) / abs(want) <= 1e-12
+
+
+def test_grouped_repeatable_and_in_any_order(torch_cuda):
+    # a problem's result does not depend on what else is in the batch or on
+    # its position: the same problems in reverse order and a batch of one
+    from paper_2306_00358_amd import Context, hotrg_run_grouped
+
+    P, O = _mixed_batch()
+    P, O = P[:6], O[:6]
+    with Context(0) as ctx:
+        a, _ = hotrg_run_grouped(ctx, P, O)
+        b, _ = hotrg_run_grouped(ctx, P[::-1], O[::-1])
+        c, _ = hotrg_run_grouped(ctx, P[:1], O[:1])
+    for x, y in zip(a, b[::-1]):
+        assert x["lnz_per_site"] == y["lnz_per_site"]
+    assert c[0]["lnz_per_site"] == a[0]["lnz_per_site"]
