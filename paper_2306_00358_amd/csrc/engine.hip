@@ -797,7 +797,7 @@ namespace {
 // device table of products, batched eigensolver and bookkeeping kernels), and
 // the whole sweep is captured once as a HIP graph and replayed.
 
-constexpr int kGroupRounds = 7;          // Rayleigh-Ritz checks per step
+constexpr int kGroupRounds = 9;          // Rayleigh-Ritz checks per step
 constexpr int kGroupSweepsPerRound = 4;  // subspace sweeps before each check
 constexpr double kGroupTol = 5e-14;      // residual tolerance (as do_step's solver)
 

@@ -74,17 +74,19 @@ __device__ __forceinline__ int jac_player(int q, int r, int p) {
 }
 
 // H (p x p, symmetric) -> W (p eigenvalues, ascending) and H overwritten by
-// Z^T (row c = eigenvector c, same order).  Z^T is accumulated in T2 (p x p).
-__global__ __launch_bounds__(kJacThreads) void k_group_jacobi(const GroupStep* __restrict__ d) {
+// Z^T (row c = eigenvector c, same order).  Z^T is accumulated in LDS next to
+// the matrix when both fit (vt_lds: p <= 96), else in T2 (p x p, global).
+__global__ __launch_bounds__(kJacThreads) void k_group_jacobi(const GroupStep* __restrict__ d,
+                                                              int vt_lds) {
   const GroupStep& s = d[blockIdx.x];
   if (!s.ctl->iter) return;
-  extern __shared__ double A[];            // p x p
+  extern __shared__ double A[];            // p x p (then Z^T, p x p, with vt_lds)
   __shared__ double cs_c[64], cs_s[64];    // rotation of pair m
   __shared__ int pi[64], pj[64];           // its indices, pi < pj
   __shared__ int rot;
   __shared__ int rank_s[128];
   const int p = s.p, h = p / 2, t = threadIdx.x;
-  double* Vt = s.T2;
+  double* Vt = vt_lds ? A + p * p : s.T2;
   for (int e = t; e < p * p; e += kJacThreads) {
     A[e] = s.H[e];
     Vt[e] = (e / p == e % p) ? 1.0 : 0.0;
@@ -319,11 +321,13 @@ void group_jacobi(const GroupStep* d, int count, int pmax, hipStream_t s) {
   static bool lds_set = [] {
     return hipFuncSetAttribute((const void*)k_group_jacobi,
                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                               128 * 128 * (int)sizeof(double)) == hipSuccess;
+                               2 * 96 * 96 * (int)sizeof(double)) == hipSuccess;
   }();
   (void)lds_set;
+  // the matrix and its eigenvectors both in LDS up to p = 96 (144 KB)
+  const int vt_lds = pmax <= 96 ? 1 : 0;
   hipLaunchKernelGGL(k_group_jacobi, dim3(count), dim3(kJacThreads),
-                     (size_t)pmax * pmax * sizeof(double), s, d);
+                     (size_t)(vt_lds + 1) * pmax * pmax * sizeof(double), s, d, vt_lds);
 }
 void group_resid(const GroupStep* d, int count, bool last, hipStream_t s) {
   hipLaunchKernelGGL(k_group_resid, dim3(count), dim3(256), 0, s, d, last ? 1 : 0);
