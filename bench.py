@@ -53,7 +53,7 @@ DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}
 # FETCH_SIZE / WRITE_SIZE counter runs of `bench.py --kernel-probe` (scaled by
 # the readings of a 1 GiB copy); the summary and commands are under profiles/.
 # An entry is valid only for the kernel version it was measured on.
-TRAFFIC = {("fp64", 64): 9.648e10}
+TRAFFIC = {("fp64", 64): 9.648e10, ("fp32", 64): 5.090e10, ("bf16x3", 64): 5.144e10}
 
 
 def parse():
@@ -92,8 +92,10 @@ def parse():
 
 def kernel_probe(args):
     """One launch of each coarse contraction at D = d_cut (the shape of a
-    steady-state benchmark step) on seeded inputs, preceded by a device copy
-    of exactly 1 GiB whose counter readings calibrate FETCH_SIZE/WRITE_SIZE."""
+    steady-state benchmark step) in --prec arithmetic on seeded inputs,
+    preceded by a device copy of exactly 1 GiB whose counter readings
+    calibrate FETCH_SIZE/WRITE_SIZE.  (With the tuner on, the candidates of
+    each product shape run too: set HOTRG_AUTOTUNE=0 and force the tile.)"""
     import torch
 
     from paper_2306_00358_amd import Context, hotrg_coarse
@@ -109,9 +111,10 @@ def kernel_probe(args):
     U = torch.rand((D, D, D), dtype=torch.float64, device="cuda", generator=g)
     Tt = torch.empty_like(T)
     with Context(0) as ctx:
-        hotrg_coarse(ctx, T, U, Tt)
+        hotrg_coarse(ctx, T, U, Tt, prec=args.prec)
     torch.cuda.synchronize()
-    print(json.dumps({"kernel_probe": {"d": D, "copy_bytes": 8 * n}}), flush=True)
+    print(json.dumps({"kernel_probe": {"d": D, "prec": args.prec, "copy_bytes": 8 * n}}),
+          flush=True)
 
 
 def xy_batch_problems(prec):
@@ -688,6 +691,8 @@ def main():
             m = measure(prec, runs=runs, warmup=1)
             m["speedup_vs_" + args.prec] = m["steps_per_s"] / head["steps_per_s"]
             m["c2_frac_of_peak"] = m["c2_tflops"] / PEAKS[prec]
+            # HBM bytes of one C2 launch (counters, profiles/), for this kernel version
+            m["c2_traffic_bytes"] = TRAFFIC.get((prec, args.d_cut))
             if prec == "bf16x3":
                 # three bf16 products are issued per multiply-add
                 m["c2_issued_frac_of_peak"] = 3 * m["c2_tflops"] / PEAKS[prec]
