@@ -439,10 +439,12 @@ def serve_record(args, rate_tflops, n=20, tol=1e-7):
 
 def small_case(ctx, reps=20):
     """The small configuration (Ising at T_c, D_cut = 8, 20 directional steps,
-    FP64): launch- and latency-bound; steps/s over `reps` runs."""
+    FP64): launch- and latency-bound; steps/s over `reps` runs, step by step
+    (hotrg_run) and with the steady steps replayed as one captured HIP graph
+    per sweep (hotrg_run_grouped with one problem)."""
     import torch
 
-    from paper_2306_00358_amd import hotrg_run, make_opts, model_params
+    from paper_2306_00358_amd import hotrg_run, hotrg_run_grouped, make_opts, model_params
 
     params = model_params("ising", beta=BETA_C)
     opts = make_opts(8, 20)
@@ -453,9 +455,19 @@ def small_case(ctx, reps=20):
         r = hotrg_run(ctx, params, opts)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / reps
+    hotrg_run_grouped(ctx, [params], [opts])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g = hotrg_run_grouped(ctx, [params], [opts])[0][0]
+    torch.cuda.synchronize()
+    dg = (time.perf_counter() - t0) / reps
     return {"workload": "Ising T_c, D_cut=8, 20 directional steps, fp64", "steps_per_s": 20 / dt,
             "ms_per_run": dt * 1e3,
-            "rel_err_vs_onsager": abs(r["lnz_per_site"] - ONSAGER_TC) / ONSAGER_TC}
+            "rel_err_vs_onsager": abs(r["lnz_per_site"] - ONSAGER_TC) / ONSAGER_TC,
+            "graph": {"steps_per_s": 20 / dg, "ms_per_run": dg * 1e3,
+                      "rel_diff_vs_step_by_step": abs(g["lnz_per_site"] - r["lnz_per_site"])
+                      / abs(r["lnz_per_site"])}}
 
 
 def mid_case(ctx, reps=3):

@@ -807,6 +807,7 @@ struct GProb {
   hotrg_state* st = nullptr;
   std::vector<int> dxs, dys, dns;
   int D = 0, n = 0, p = 0, need = 0, sp = HOTRG_FP64;  // steady dims, block size, precision
+  bool dense = false;  // environment diagonalised whole (n <= 96) instead of a block
   Buf M, eig, U, scal, Tt, U1, U3;
   Buf RA1[2], RA2[2], RX1[2], RX2[2], RU1[2], RU3[2];
   GroupCtl* ctl = nullptr;  // device
@@ -822,6 +823,7 @@ struct GTable {  // a grouped launch's device table
 
 struct GRun {
   std::vector<GProb*> act;
+  bool dense = false;  // all problems' environments diagonalised whole
   int sp = HOTRG_FP64, mode = RP_F32, pmax = 16;
   long long max_pn = 1;
   GroupStep* steps = nullptr;
@@ -906,15 +908,17 @@ void group_sweep(hotrg_ctx* c, GRun& R, bool tune, std::vector<std::vector<long 
     launch_symmetrize((double*)g->M.p, g->n, s);
     launch_trace((const double*)g->M.p, g->n, (double*)((char*)g->scal.p + 8), s);
   }
-  // leading eigenpairs: block subspace iteration with a fixed budget
+  // leading eigenpairs: block subspace iteration with a fixed budget, or the
+  // whole (small) environment by Jacobi
   group_begin(R.steps, G, s);
-  group_seed(R.steps, G, R.max_pn, s);
+  if (R.dense) group_dense(R.steps, G, R.pmax, s);
+  if (!R.dense) group_seed(R.steps, G, R.max_pn, s);
   auto pass = [&](const GTable& gram, int ps, bool full, const GTable& apply) {
     launch_f64_table(gram, B_KCONTIG, s);
     launch_chol_inv_batched(R.chol, G, R.pmax, ps, full, s);
     launch_f64_table(apply, B_NCONTIG, s);
   };
-  for (int round = 0; round < kGroupRounds; ++round) {
+  for (int round = 0; round < (R.dense ? 0 : kGroupRounds); ++round) {
     for (int sw = 0; sw < kGroupSweepsPerRound; ++sw) {
       const bool full = sw == kGroupSweepsPerRound - 1;
       launch_f64_table(R.vm, B_NCONTIG, s);  // Y = V M
@@ -1072,6 +1076,7 @@ void group_tables(hotrg_ctx* c, GRun& R, Buf& store, std::vector<std::vector<lon
     d.K = g->o.n_steps;
     d.tau = g->o.degen_tol;
     d.tol = kGroupTol;
+    d.M = (const double*)g->M.p;
     d.V = e;
     d.Y = e + pn;
     d.T2 = e + 2 * pn;
@@ -1241,6 +1246,7 @@ void run_grouped_impl(hotrg_ctx* c, int N, const hotrg_model_params* params,
   std::vector<char> done(N, 0);
   // plan: the steady step of each problem and whether the batch takes it
   int group_sp = -1;
+  bool group_dense_kind = false;
   for (int i = 0; i < N; ++i) {
     GProb& g = P[i];
     g.idx = i;
@@ -1275,10 +1281,17 @@ void run_grouped_impl(hotrg_ctx* c, int N, const hotrg_model_params* params,
         g.n = g.D * g.D;
         g.need = std::max(g.D + 1, std::min(g.o.spec_len, g.n));
         g.p = (std::min(128, std::max(2 * g.D, g.need + 16)) + 15) / 16 * 16;
-        ok = g.need + 16 <= g.p && g.p <= 128 && 4 * g.p <= g.n;
+        const bool block = g.need + 16 <= g.p && g.p <= 128 && 4 * g.p <= g.n;
+        // small environments: Jacobi on the whole matrix, padded to even size
+        g.dense = !block && g.n <= 96;
+        if (g.dense) g.p = g.n + (g.n & 1);
+        ok = block || g.dense;
       }
-      if (ok && group_sp < 0) group_sp = g.sp;
-      g.k_host = ok && g.sp == group_sp ? ks - 1 : -1;  // -1: runs alone
+      if (ok && group_sp < 0) {
+        group_sp = g.sp;
+        group_dense_kind = g.dense;
+      }
+      g.k_host = ok && g.sp == group_sp && g.dense == group_dense_kind ? ks - 1 : -1;  // -1: alone
     });
   }
   // warm-up steps one problem at a time; problems outside the batch run whole
@@ -1361,6 +1374,7 @@ void run_grouped_impl(hotrg_ctx* c, int N, const hotrg_model_params* params,
       GRun R;
       R.sp = group_sp;
       R.mode = mode;
+      R.dense = group_dense_kind;
       std::vector<GProb*> cur;
       bool eager_done = false;
       for (;;) {

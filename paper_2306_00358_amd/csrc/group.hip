@@ -212,6 +212,30 @@ __global__ void k_group_restart(const GroupStep* __restrict__ d) {
     s.V[e] = s.X[e];
 }
 
+// Small environments (n <= 96) are diagonalised whole by the Jacobi kernel:
+// H = M padded with zero rows and columns to the even size p (a padded index
+// adds an eigenvalue 0 below the spectrum), and the eigenvectors' first n
+// components become the rows of X.
+__global__ void k_group_dense_in(const GroupStep* __restrict__ d) {
+  const GroupStep& s = d[blockIdx.y];
+  if (!s.ctl->iter) return;
+  const int p = s.p, n = s.n;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < p * p; e += gridDim.x * blockDim.x) {
+    const int i = e / p, j = e % p;
+    s.H[e] = (i < n && j < n) ? s.M[(long long)i * n + j] : 0.0;
+  }
+}
+
+__global__ void k_group_dense_out(const GroupStep* __restrict__ d) {
+  const GroupStep& s = d[blockIdx.y];
+  if (!s.ctl->iter) return;
+  const int p = s.p, n = s.n;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < p * n; e += gridDim.x * blockDim.x) {
+    const int i = e / n, j = e % n;
+    s.X[e] = s.H[(long long)i * p + j];
+  }
+}
+
 // ------------------------------------------------------------ bookkeeping --
 
 // Spectrum record of step k = ctl.k + 1 (as k_spectrum: lambda / lambda_1,
@@ -334,6 +358,11 @@ void group_resid(const GroupStep* d, int count, bool last, hipStream_t s) {
 }
 void group_restart(const GroupStep* d, int count, long long max_pn, hipStream_t s) {
   hipLaunchKernelGGL(k_group_restart, dim3(gblocks(max_pn), count), dim3(256), 0, s, d);
+}
+void group_dense(const GroupStep* d, int count, int pmax, hipStream_t s) {
+  hipLaunchKernelGGL(k_group_dense_in, dim3(16, count), dim3(256), 0, s, d);
+  group_jacobi(d, count, pmax, s);
+  hipLaunchKernelGGL(k_group_dense_out, dim3(16, count), dim3(256), 0, s, d);
 }
 void group_spectrum(const GroupStep* d, int count, hipStream_t s) {
   hipLaunchKernelGGL(k_group_spectrum, dim3(count), dim3(256), 0, s, d);

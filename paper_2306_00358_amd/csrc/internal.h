@@ -217,6 +217,7 @@ struct GroupStep {
   GroupCtl* ctl;
   int n, dn, dy, p, need, trunc, spec_len, K;
   double tau, tol;
+  const double* M;  // environment (n x n)
   double* trace;
   double* W;
   double* X;
@@ -235,6 +236,8 @@ void group_symm_h(const GroupStep* d, int count, hipStream_t s);
 void group_jacobi(const GroupStep* d, int count, int pmax, hipStream_t s);
 void group_resid(const GroupStep* d, int count, bool last, hipStream_t s);
 void group_restart(const GroupStep* d, int count, long long max_pn, hipStream_t s);
+// whole small environments (n <= 96, p = n rounded up to even) by Jacobi
+void group_dense(const GroupStep* d, int count, int pmax, hipStream_t s);
 void group_spectrum(const GroupStep* d, int count, hipStream_t s);
 void group_norm(const GroupStep* d, int count, hipStream_t s);
 void group_zero_max(const GroupStep* d, int count, hipStream_t s);

@@ -113,3 +113,32 @@ def test_grouped_repeatable_and_in_any_order(torch_cuda):
     for x, y in zip(a, b[::-1]):
         assert x["lnz_per_site"] == y["lnz_per_site"]
     assert c[0]["lnz_per_site"] == a[0]["lnz_per_site"]
+
+
+def test_grouped_small_environments_dense_jacobi(torch_cuda):
+    # environments of at most 96 rows are diagonalised whole by the Jacobi
+    # kernel (odd sizes padded to even): D_cut = 8 (n = 64) and 9 (n = 81)
+    from paper_2306_00358_amd import Context, hotrg_run, hotrg_run_grouped, make_opts, model_params
+
+    cases = [("ising", BETA_C, 0, 8, 20), ("ising", 0.42, 0, 9, 16), ("xy", 1.1, 1, 8, 14),
+             ("potts", math.log(1 + math.sqrt(3)), 0, 9, 12)]
+    P = [model_params(m, beta=b, n_max=nm, q=3) for m, b, nm, _, _ in cases]
+    O = [make_opts(d, K, spec_len=6, **(dict(trunc="multiplet", degen_tol=1e-5) if m == "xy" else {}))
+         for m, _, _, d, K in cases]
+    with Context(0) as ctx:
+        got, st = hotrg_run_grouped(ctx, P, O, with_steps=True)
+        stats = ctx.group_stats()
+        alone = [hotrg_run(ctx, p, o) for p, o in zip(P, O)]
+    say("group stats", stats)
+    assert st == [0] * len(cases)
+    assert stats["replays"] >= 5 and stats["fallbacks"] == 0
+    for (m, b, nm, d, K), o, g, a in zip(cases, O, got, alone):
+        T0 = {"ising": lambda: tensors.ising(b), "xy": lambda: tensors.xy(b, nm),
+              "potts": lambda: tensors.potts(b, 3)}[m]()
+        want = hotrg.run(T0, d, K, "multiplet" if o.trunc else "plain", o.degen_tol, spec_len=6)
+        rel = abs(g["lnz_per_site"] - want.lnz_per_site) / abs(want.lnz_per_site)
+        say(m, d, K, "vs oracle", rel, "vs alone", abs(g["lnz_per_site"] - a["lnz_per_site"]))
+        assert rel <= 1e-12
+        assert [s["kept"] for s in g["steps"]] == [s.kept for s in want.steps]
+        for gs, ws in zip(g["spectra"], want.spectra):
+            assert np.abs(np.asarray(gs[:len(ws)]) - ws).max() <= 1e-12
