@@ -7,15 +7,14 @@ cut falls at a noise-level gap (ordered phase), two correct FP64
 implementations drift apart by far more than one rounding error.  This
 module measures the drift of the oracle against itself when the environment
 M of every step is perturbed by a seeded symmetric random matrix of relative
-size 2^-52 (one rounding error); the parity tolerance of step k is then
+size 2^-52 (one rounding error); the spectra tolerance of step k is then
 max(floor, factor * drift_k).  The same perturbed run gives the drift of
-ln Z/N and the kept counts a perturbed but correct run may choose; the
-ln Z/N tolerance is max(floor, factor * lnz drift), and kept counts are
-compared only at steps where the perturbed run kept the same number and
-every gap the multiplet rule looks at clears the threshold by more than the
-spectra tolerance allows the values to move (`cut_is_robust`): the rule is a
-step function of the spectrum, so at a gap within that distance of tau both
-cuts are correct results.
+ln Z/N and the kept counts a perturbed but correct run chooses: a parity case
+is *conditioned* when the kept counts do not move, ln Z/N moves far below the
+1e-12 bar, and every gap the multiplet rule looks at clears the threshold by
+more than the spectra can move (`cut_is_robust`: the rule is a step function
+of the spectrum, so at a gap within that distance of tau both cuts would be
+correct results).  Only conditioned cases are held to 1e-12 on ln Z/N.
 """
 
 import numpy as np
@@ -24,10 +23,6 @@ from oracle import hotrg
 
 SPEC_FLOOR = 1e-12
 SPEC_FACTOR = 100.0
-
-
-LNZ_FLOOR = 1e-12
-LNZ_FACTOR = 100.0
 
 
 def oracle_drift(T0, d_cut, n_steps, spec_len, trunc="plain", tau=1e-10, seed=0, base=None):
@@ -64,10 +59,6 @@ def spectra_drift(T0, d_cut, n_steps, spec_len, trunc="plain", tau=1e-10, seed=0
 
 def spectra_tolerances(drift):
     return [max(SPEC_FLOOR, SPEC_FACTOR * d) for d in drift]
-
-
-def lnz_tolerance(lnz_drift):
-    return max(LNZ_FLOOR, LNZ_FACTOR * lnz_drift)
 
 
 def cut_is_robust(spectrum, n, d_new, tau, delta):
