@@ -15,7 +15,10 @@
 //
 // Tiling: 8 waves, 256 x 256 block tile, each wave 128 x 64 as 8 x 4 MFMA
 // tiles (256 x 128 and 64 x 64 per wave when N < 256); K slabs of 32 elements streamed into LDS with
-// global_load_lds_dwordx4 (16 bytes per lane), two LDS stages.  An LDS row
+// global_load_lds_dwordx4 (16 bytes per lane), two LDS stages and one
+// barrier per slab (a three-stage form software-pipelines the fragment reads
+// across slabs).  The split-BF16 products of a slab start after five of its
+// 24 fragment reads; the rest are placed among the MFMAs.  An LDS row
 // is 128 bytes = 8 chunks of 16 bytes: for RP_F32 the 32 floats of the slab,
 // for RP_BF16X3 four hi chunks then four lo chunks (8 bf16 each).  Chunk c
 // of row r sits at chunk position c ^ ((r >> 1) & 7), so the 16 rows read by
@@ -218,22 +221,76 @@ __device__ __forceinline__ void rp_tile(const void* __restrict__ Ahi, const void
     if (s < nslab) slab(s, no{}, no{});
   } else
   for (int s = 0; s < nslab; ++s) {
-    const int cur = NST == 2 ? (s & 1) : s % 3;
-    if (NST == 2 && s + 1 < nslab) {
-      issue((s + 1) * 32, cur ^ 1);
-      asm volatile("s_waitcnt vmcnt(%0)" ::"n"(LOADS) : "memory");
-    } else if (NST == 3 && s + 1 < nslab) {
-      asm volatile("s_waitcnt vmcnt(%0)" ::"n"(LOADS) : "memory");  // slab s+1 may be pending
-    } else {
-      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    }
-    // slab s has landed for every wave; with three stages every wave has also
-    // finished reading slab s-1, whose stage takes slab s+2
+    // two stages: slab s has landed for every wave, and every wave has read
+    // slab s-1 (its reads were waited for at the end of that slab), whose
+    // stage then takes slab s+1.  One barrier per slab.
+    const int cur = s & 1;
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");
-    if (NST == 3 && s + 2 < nslab) issue((s + 2) * 32, (s + 2) % 3);
+    if (s + 1 < nslab) issue((s + 1) * 32, cur ^ 1);
     const char* as = smem + cur * STAGE;
     const char* bs = as + A_BYTES;
+    if constexpr (MODE == RP_BF16X3) {
+      // fragments read as they are needed: the lo half of row tile 0 and the
+      // hi half of B first (the first four products use only those), the
+      // other five during those products, row tile i+1 of A during the
+      // products of row tile i; the order of the products into each
+      // accumulator (lo*hi, hi*lo, hi*hi, slab by slab) is unchanged
+      f4 fh[TM], fl[TM], gh[4], gl[4];
+      auto rd = [&](const char* base, int r, int c) {
+        return *(const f4*)(base + r * 128 + ((c ^ rp_swz(r)) << 4));
+      };
+      const int ra = wm * 16 * TM + li, rb = wn * 64 + li;
+      fl[0] = rd(as, ra, c1);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) gh[j] = rd(bs, rb + 16 * j, c0);
+      fh[0] = rd(as, ra, c0);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) gl[j] = rd(bs, rb + 16 * j, c1);
+      __builtin_amdgcn_sched_group_barrier(0x100, 5, 0);  // 5 LDS reads
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        if (i + 1 < TM) {
+          fh[i + 1] = rd(as, ra + 16 * (i + 1), c0);
+          fl[i + 1] = rd(as, ra + 16 * (i + 1), c1);
+        }
+        const bf8 ah = __builtin_bit_cast(bf8, fh[i]);
+        const bf8 al = __builtin_bit_cast(bf8, fl[i]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, __builtin_bit_cast(bf8, gh[j]),
+                                                              acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, __builtin_bit_cast(bf8, gl[j]),
+                                                              acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, __builtin_bit_cast(bf8, gh[j]),
+                                                              acc[i][j], 0, 0, 0);
+        // placement (0x008 = MFMA, 0x100 = LDS read)
+        if (i == 0) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+          __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+          __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+          __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+          __builtin_amdgcn_sched_group_barrier(0x008, 5, 0);
+          __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+          __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+          __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+          __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+        } else {
+          __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
+          __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+          __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
+          __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+          __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
+        }
+      }
+    } else {
     f4 a0[TM], a1[TM], b0[4], b1[4];
 #pragma unroll
     for (int i = 0; i < TM; ++i) {
@@ -247,37 +304,18 @@ __device__ __forceinline__ void rp_tile(const void* __restrict__ Ahi, const void
       b0[j] = *(const f4*)(bs + r * 128 + ((c0 ^ rp_swz(r)) << 4));
       b1[j] = *(const f4*)(bs + r * 128 + ((c1 ^ rp_swz(r)) << 4));
     }
-    if (MODE == RP_F32) {
 #pragma unroll
-      for (int t = 0; t < 8; ++t)
+    for (int t = 0; t < 8; ++t)
 #pragma unroll
-        for (int i = 0; i < TM; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const float av = t < 4 ? a0[i][t] : a1[i][t - 4];
-            const float bv = t < 4 ? b0[j][t] : b1[j][t - 4];
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[i][j], 0, 0, 0);
-          }
-    } else {
-#pragma unroll
-      for (int i = 0; i < TM; ++i) {
-        const bf8 ah = __builtin_bit_cast(bf8, a0[i]);
-        const bf8 al = __builtin_bit_cast(bf8, a1[i]);
+      for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const bf8 bh = __builtin_bit_cast(bf8, b0[j]);
-          const bf8 bl = __builtin_bit_cast(bf8, b1[j]);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[i][j], 0, 0, 0);
+          const float av = t < 4 ? a0[i][t] : a1[i][t - 4];
+          const float bv = t < 4 ? b0[j][t] : b1[j][t - 4];
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[i][j], 0, 0, 0);
         }
-      }
     }
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-    if (NST == 2) {
-      __builtin_amdgcn_s_barrier();
-      asm volatile("" ::: "memory");
-    }
   }
 
   float mx = 0.f;
