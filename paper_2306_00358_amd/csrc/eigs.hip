@@ -47,6 +47,8 @@
 
 namespace hotrg {
 
+typedef double d4 __attribute__((ext_vector_type(4)));
+
 // deterministic start block: splitmix64 of the element index -> [-1, 1)
 __global__ void k_seed_block(double* V, long long count, unsigned long long seed) {
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < count;
@@ -84,9 +86,16 @@ __global__ void k_seed_block(double* V, long long count, unsigned long long seed
 // LDS for coalesced stores.  *fail is set if a pivot is not positive.
 constexpr int kCholThreads = 256;
 
+//
+// With Rout the kernel stops after the factorisation and writes the factor R
+// of the matrix factored (p x p, row-major, zeros below the diagonal) to
+// Rout and the row scaling D^-1 to Rout + p * p (ones without `scale`);
+// RinvT is not touched.  Q = R^-T D^-1 Y then comes from k_trsm_rows.
 __device__ __forceinline__ void chol_inv_body(const double* __restrict__ G, int p,
                                               double shift_rel, int scale, double identity_tol,
-                                              double* __restrict__ RinvT, int* fail) {
+                                              double* __restrict__ RinvT, int* fail,
+                                              int* missed = nullptr,
+                                              double* __restrict__ Rout = nullptr) {
   extern __shared__ double lds[];
   double* R = lds;             // p * p: R (upper, zeros below), later X^T
   double* P = R + p * p;       // 2 x 8 x 128 published rows
@@ -119,9 +128,12 @@ __device__ __forceinline__ void chol_inv_body(const double* __restrict__ G, int 
     double mx = 0.0;
     for (int i = 0; i < kCholThreads; ++i) mx = fmax(mx, dev[i]);
     if (mx <= identity_tol) {  // uniform: every thread reduced the same values
-      for (int e = t; e < p * p; e += kCholThreads) RinvT[e] = (e / p == e % p) ? 1.0 : 0.0;
+      double* out = Rout ? Rout : RinvT;
+      for (int e = t; e < p * p; e += kCholThreads) out[e] = (e / p == e % p) ? 1.0 : 0.0;
+      if (Rout && t < p) Rout[p * p + t] = 1.0;
       return;
     }
+    if (missed && t == 0) *missed += 1;  // the check found a real factorisation to do
   }
   for (int e = t; e < p * p; e += kCholThreads) R[e] = 0.0;
   // diagonal: the owners publish it
@@ -247,6 +259,13 @@ __device__ __forceinline__ void chol_inv_body(const double* __restrict__ G, int 
       }
     }
   }
+  if (Rout) {
+    // every block's rows of R were written before the barrier that opened
+    // its trailing update
+    for (int e = t; e < p * p; e += kCholThreads) Rout[e] = R[e];
+    if (t < p) Rout[p * p + t] = dsc[t];
+    return;
+  }
   // X = I in registers
 #pragma unroll
   for (int a = 0; a < 8; ++a)
@@ -333,8 +352,106 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_inv(const double* __restr
                                                            double shift_rel, int scale,
                                                            double identity_tol,
                                                            double* __restrict__ RinvT,
-                                                           int* fail) {
-  chol_inv_body(G, p, shift_rel, scale, identity_tol, RinvT, fail);
+                                                           int* fail, int* missed,
+                                                           double* __restrict__ Rout) {
+  chol_inv_body(G, p, shift_rel, scale, identity_tol, RinvT, fail, missed, Rout);
+}
+
+// Q = R^-T D^-1 Y for the rows of Y (p x n, row-major): with L = R^T (lower
+// triangular), L Q = D^-1 Y is solved by blocks of 16 rows,
+//   Q_b = L_bb^-1 (D_b^-1 Y_b - sum_{a<b} L_ba Q_a),
+// where R and D^-1 are the output of k_chol_inv with Rout (R at Rf, D^-1 at
+// Rf + p * p).  One workgroup per 64 columns; each of its 4 waves owns 16
+// columns and keeps their Q blocks in registers: in the accumulator layout of
+// v_mfma_f64_16x16x4f64 (lane j + 16 l holds rows l + 4 v of column j) value
+// v of a lane is exactly the B operand the next products take at k step v,
+// so the blocks never leave the registers until the end.  R is staged in LDS
+// (the A operands of every wave) and the 16 x 16 inverses of the diagonal
+// blocks are formed there by forward substitution, one column per thread.
+// p a multiple of 16, at most 128; columns past n are computed but not
+// stored.
+constexpr int kTrsmCols = 64;
+__global__ __launch_bounds__(256) void k_trsm_rows(const double* __restrict__ Rf, int p,
+                                                   const double* __restrict__ Y, int n,
+                                                   double* __restrict__ Q) {
+  extern __shared__ double lds[];
+  double* Rs = lds;              // p x p
+  double* Li = lds + p * p;      // p / 16 blocks of 16 x 16: Li[b][i][c]
+  const double* dinv = Rf + p * p;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int nb = p >> 4;
+  const int j = lane & 15, l = lane >> 4;
+  const int col = blockIdx.x * kTrsmCols + wave * 16 + j;
+  const int cc = col < n ? col : n - 1;
+  // this lane's rows of D^-1 Y, loaded before anything waits on them
+  d4 y[8];
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    if (b >= nb) break;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * b + l + 4 * v;
+      y[b][v] = Y[(long long)r * n + cc];
+    }
+  }
+  {
+    // p * p is a multiple of 256 doubles: 16-byte copies, 8 in flight
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const d2* src = (const d2*)Rf;
+    d2* dst = (d2*)Rs;
+#pragma unroll 8
+    for (int e = t; e < p * p / 2; e += 256) dst[e] = src[e];
+  }
+  __syncthreads();
+  if (t < 16 * nb) {
+    // column c of the inverse of L_bb, L_bb[i][j] = R[16b + j][16b + i]
+    const int b = t >> 4, c = t & 15, o = 16 * b;
+    double x[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      double v = i == c ? 1.0 : 0.0;
+#pragma unroll
+      for (int j = 0; j < i; ++j) v -= Rs[(o + j) * p + o + i] * x[j];
+      x[i] = v / Rs[(o + i) * p + o + i];
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) Li[(b * 16 + i) * 16 + c] = x[i];
+  }
+  __syncthreads();
+  d4 q[8];
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    if (b >= nb) break;
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      if (a >= b) break;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        // A[i][k] = L[16b + i][16a + 4s + k] = R[16a + 4s + k][16b + i], lane i + 16k
+        const double av = Rs[(16 * a + 4 * s + l) * p + 16 * b + j];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, q[a][s], acc, 0, 0, 0);
+      }
+    }
+    d4 x;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) x[v] = dinv[16 * b + l + 4 * v] * y[b][v] - acc[v];
+    d4 qb = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const double av = Li[(b * 16 + j) * 16 + 4 * s + l];
+      qb = __builtin_amdgcn_mfma_f64_16x16x4f64(av, x[s], qb, 0, 0, 0);
+    }
+    q[b] = qb;
+  }
+  if (col < n) {
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      if (b >= nb) break;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Q[(long long)(16 * b + l + 4 * v) * n + col] = q[b][v];
+    }
+  }
 }
 
 // One workgroup per problem of a batch; a problem whose gate reads 0 (its
@@ -411,8 +528,8 @@ void launch_trace(const double* M, int n, double* out, hipStream_t s) {
 }
 
 static inline int splitk_chunk(int K) {
-  // about 64 partial products, each K chunk a multiple of 16
-  int c = (K + 63) / 64;
+  // about 32 partial products, each K chunk a multiple of 16
+  int c = (K + 31) / 32;
   c = (c + 15) / 16 * 16;
   return c < 16 ? 16 : c;
 }
@@ -435,9 +552,26 @@ size_t topk_workspace_doubles(int n, int p) {
 
 // Returns true and leaves theta (ascending, p values) in W and the Ritz
 // vectors (rows, same order) in Xout (p x n) on convergence.
+//
+// The sweeps multiply by M - sigma I (the Rayleigh-Ritz products use M
+// itself).  M is positive semidefinite and the unwanted eigenvalues lie in
+// [0, lambda_{p+1}]; with sigma = lambda_{p+1} / 2 the worst of them shrinks
+// by sigma / (lambda_need - sigma) per sweep instead of lambda_{p+1} /
+// lambda_need.  *shift holds the sigma to start with (from an earlier solve
+// of the same kind; 0 if none) and returns theta_min / 2 of the last
+// Rayleigh-Ritz step (theta_min <= lambda_p, so sigma never exceeds half of
+// a wanted eigenvalue).
+//
+// Between Rayleigh-Ritz steps a sweep orthonormalises with one shifted
+// Cholesky-QR pass and checks the result with a second Gram matrix (a real
+// second pass when it is not the identity to 1e-2).  When no check since the
+// last Rayleigh-Ritz step needed that second pass, only the first sweep of
+// the next group is checked; *nocheck carries that state to the next solve.
+// Every Rayleigh-Ritz step still sees a basis from three passes, and its
+// residuals decide convergence.
 bool topk_eigs(rocblas_handle blas, const double* M, int n, int p, int need, double tol,
-               int q_first, double* ws, double* W, double* Xout, int* dinfo, int* iters,
-               int* enough, double* resid, hipStream_t s) {
+               int q_first, double* shift, int* nocheck, double* ws, double* W, double* Xout,
+               int* dinfo, int* iters, int* enough, double* resid, hipStream_t s) {
   const size_t pn = (size_t)p * n, pp = (size_t)p * p;
   const int kc = splitk_chunk(n);
   const int kv = vm_chunk(n);
@@ -451,7 +585,10 @@ bool topk_eigs(rocblas_handle blas, const double* M, int n, int p, int need, dou
   double* H = Rt + pp;
   double* E = H + pp;          // p (tridiagonal work for dsyevd)
   double* res = E + pp;        // p
-  int* fail = (int*)(res + p); // 1 int
+  int* fail = (int*)(res + p); // fail flag, then the count of checks that missed
+  // a pass's Cholesky factor (p x p) at Rt and its row scaling (p) in the
+  // first p entries of H, which only the Rayleigh-Ritz step uses
+  double* Rf = Rt;
   const size_t lds = ((size_t)p * p + 2048) * sizeof(double);
   const double u = std::ldexp(1.0, -53);
   const double shift_rel = 11.0 * ((double)n * p + (double)p * (p + 1)) * u;
@@ -459,10 +596,15 @@ bool topk_eigs(rocblas_handle blas, const double* M, int n, int p, int need, dou
   static bool lds_set = [] {
     return hipFuncSetAttribute((const void*)k_chol_inv, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)(((size_t)128 * 128 + 2048) * sizeof(double))) ==
-           hipSuccess;
+               hipSuccess &&
+           hipFuncSetAttribute((const void*)k_trsm_rows,
+                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)(((size_t)128 * 128 + 128 * 16) * sizeof(double))) ==
+               hipSuccess;
   }();
+  const size_t trsm_lds = ((size_t)p * p + (size_t)p * 16) * sizeof(double);
   if (!lds_set || p > 128 || p % 16 != 0) return false;
-  (void)hipMemsetAsync(fail, 0, sizeof(int), s);
+  (void)hipMemsetAsync(fail, 0, 2 * sizeof(int), s);
   hipLaunchKernelGGL(k_seed_block, dim3(256), dim3(256), 0, s, V, (long long)pn, 12345ULL);
 
   // one orthonormalisation of rows of Y into V: shifted Cholesky-QR of the
@@ -470,24 +612,27 @@ bool topk_eigs(rocblas_handle blas, const double* M, int n, int p, int need, dou
   // Rayleigh-Ritz check (`full`); between checks only the first two, the
   // second skipped on the device (R^-1 = I) when its Gram matrix is the
   // identity to 1e-2.
-  auto orth = [&](const double* Yin, double* Vout, bool full) {
+  auto orth = [&](const double* Yin, double* Vout, bool full, bool check) {
     const double* src = Yin;
-    const int last = full ? 2 : 1;
+    const int last = full ? 2 : (check ? 1 : 0);
     for (int pass = 0; pass <= last; ++pass) {
       gemm_f64_splitk(src, n, src, n, B_KCONTIG, G, p, p, p, n, kc, part, s);
       hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(kCholThreads), lds, s, G, p,
                          pass < 2 ? shift_rel : 0.0, pass < 2 ? 1 : 0,
-                         (pass == 0 || full) ? 0.0 : 1e-2, Rt, fail);
+                         (pass == 0 || full) ? 0.0 : 1e-2, Rt, fail, fail + 1, Rf);
       double* dst = (pass == last) ? Vout : (src == T2 ? Y : T2);
       if (dst == src) dst = (src == Y) ? T2 : Y;
-      gemm_f64(Rt, p, src, n, B_NCONTIG, dst, out_rowmajor(n), p, n, p, nullptr, s);
+      hipLaunchKernelGGL(k_trsm_rows, dim3((n + kTrsmCols - 1) / kTrsmCols), dim3(256), trsm_lds,
+                         s, (const double*)Rf, p, src, n, dst);
       src = dst;
     }
   };
 
-  // Y = V M
-  auto vm = [&](const double* Vin, double* Yout) {
-    gemm_f64_splitk(Vin, n, M, n, B_NCONTIG, Yout, n, p, n, n, kv, part, s);
+  // Y = V (M - sigma I)
+  double sigma = shift && *shift > 0.0 ? *shift : 0.0;
+  auto vm = [&](const double* Vin, double* Yout, double sg) {
+    gemm_f64_splitk(Vin, n, M, n, B_NCONTIG, Yout, n, p, n, n, kv, part, s,
+                    sg > 0.0 ? Vin : nullptr, sg);
   };
 
   int it = 0, q = q_first > 0 ? q_first : 3;
@@ -495,13 +640,14 @@ bool topk_eigs(rocblas_handle blas, const double* M, int n, int p, int need, dou
   double prev = 1e300;
   std::vector<double> th(p), rs(p);
   while (true) {
+    const bool skip = nocheck && *nocheck;
     for (int r = 0; r < q; ++r) {
-      vm(V, Y);
-      orth(Y, V, r == q - 1);
+      vm(V, Y, sigma);
+      orth(Y, V, r == q - 1, r == 0 || !skip);
       ++it;
     }
     // Rayleigh-Ritz
-    vm(V, Y);
+    vm(V, Y, 0.0);
     gemm_f64_splitk(V, n, Y, n, B_KCONTIG, H, p, p, p, n, kc, part, s);
     hipLaunchKernelGGL(k_symmetrize_small, dim3(16), dim3(256), 0, s, H, p);
     if (rocsolver_dsyevd(blas, rocblas_evect_original, rocblas_fill_lower, p, H, p, W, E, dinfo) !=
@@ -511,19 +657,27 @@ bool topk_eigs(rocblas_handle blas, const double* M, int n, int p, int need, dou
     gemm_f64(H, p, V, n, B_NCONTIG, Xout, out_rowmajor(n), p, n, p, nullptr, s);
     gemm_f64(H, p, Y, n, B_NCONTIG, Yx, out_rowmajor(n), p, n, p, nullptr, s);
     hipLaunchKernelGGL(k_ritz_residual, dim3(p), dim3(256), 0, s, Yx, Xout, W, n, res);
-    int hinfo[2] = {0, 0};
+    int hinfo[3] = {0, 0, 0};
     (void)hipMemcpyAsync(th.data(), W, p * sizeof(double), hipMemcpyDeviceToHost, s);
     (void)hipMemcpyAsync(rs.data(), res, p * sizeof(double), hipMemcpyDeviceToHost, s);
     (void)hipMemcpyAsync(&hinfo[0], dinfo, sizeof(int), hipMemcpyDeviceToHost, s);
-    (void)hipMemcpyAsync(&hinfo[1], fail, sizeof(int), hipMemcpyDeviceToHost, s);
+    (void)hipMemcpyAsync(&hinfo[1], fail, 2 * sizeof(int), hipMemcpyDeviceToHost, s);
     if (hipStreamSynchronize(s) != hipSuccess) return false;
     if (hinfo[0] != 0 || hinfo[1] != 0) return false;
+    if (nocheck) *nocheck = hinfo[2] == 0 ? 1 : 0;
+    (void)hipMemsetAsync(fail + 1, 0, sizeof(int), s);
     const double t1 = th[p - 1];
     if (!(t1 > 0.0)) return false;
     double top = 0.0;
     for (int i = 0; i < need; ++i) top = std::fmax(top, rs[p - 1 - i] / t1);
-    double rate = th[p - need] > 0.0 ? th[0] / th[p - need] : 0.5;
+    // the worst unwanted factor per sweep at the shift the sweeps used, and
+    // the shift for the next ones
+    const double lo = std::fmax(th[0], 0.0);
+    double rate = th[p - need] > sigma ? std::fmax(lo - sigma, sigma) / (th[p - need] - sigma)
+                                       : 0.5;
     rate = std::fmin(std::fmax(rate, 1e-6), 0.95);
+    sigma = 0.5 * lo;
+    if (shift) *shift = sigma;
     if (iters) *iters = it;
     if (resid) *resid = top;
     if (top <= tol) {
@@ -535,6 +689,9 @@ bool topk_eigs(rocblas_handle blas, const double* M, int n, int p, int need, dou
     }
     if (it >= max_it || !(top < 0.5 * prev)) return false;
     prev = top;
+    // the sweeps to come run at the new shift
+    rate = th[p - need] > sigma ? std::fmax(lo - sigma, sigma) / (th[p - need] - sigma) : 0.5;
+    rate = std::fmin(std::fmax(rate, 1e-6), 0.95);
     q = (int)std::ceil(std::log(tol / top) / std::log(rate));
     q = q < 1 ? 1 : (q > max_it - it ? max_it - it : q);
     // continue from the Ritz vectors

@@ -128,6 +128,8 @@ struct hotrg_state {
   // sweeps the last iterative eigensolve of each step parity needed, and its n
   // ([parity + 2 * side])
   int eig_sweeps[4] = {0, 0, 0, 0}, eig_n[4] = {0, 0, 0, 0};
+  double eig_shift[4] = {0.0, 0.0, 0.0, 0.0};
+  int eig_nocheck[4] = {0, 0, 0, 0};
   // precision schedule: first step allowed in reduced precision, and the
   // a-priori error bound of the steps run reduced so far
   int first_reduced = 1;
@@ -596,8 +598,13 @@ void do_step(hotrg_ctx* c, hotrg_state* st, const hotrg_opts* o) {
       // one sweep more than the last such solve is estimated to have needed
       const int slot = (st->k & 1) + 2 * side;
       const int q_first = st->eig_n[slot] == n ? st->eig_sweeps[slot] + 1 : 3;
+      if (st->eig_n[slot] != n) {
+        st->eig_shift[slot] = 0.0;
+        st->eig_nocheck[slot] = 0;
+      }
       sub = topk_eigs(c->blas, (const double*)Mb.p, n, p, need, 5e-14, q_first,
-                      (double*)c->EW.p, (double*)Wb.p, (double*)Xb.p,
+                      &st->eig_shift[slot], &st->eig_nocheck[slot], (double*)c->EW.p,
+                      (double*)Wb.p, (double*)Xb.p,
                       (int*)((char*)c->scal.p + 48), &iters, &enough, &resid, c->stream);
       st->eig_n[slot] = sub ? n : 0;
       st->eig_sweeps[slot] = enough;

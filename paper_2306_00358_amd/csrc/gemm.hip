@@ -371,18 +371,21 @@ static void launch_f64(const double* A, long long lda, const double* B, long lon
 }
 
 __global__ void k_sum_partials(const double* __restrict__ P, int parts, long long count,
-                               long long stride, double* __restrict__ out) {
+                               long long stride, double* __restrict__ out,
+                               const double* __restrict__ sub, double sigma) {
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < count;
        e += (long long)gridDim.x * blockDim.x) {
     double s = 0.0;
+#pragma unroll 8
     for (int z = 0; z < parts; ++z) s += P[z * stride + e];
+    if (sub) s -= sigma * sub[e];
     out[e] = s;
   }
 }
 
 void gemm_f64_splitk(const double* A, long long lda, const double* B, long long ldb, int blayout,
                      double* C, long long ldc, int M, int N, int K, int kchunk, double* partials,
-                     hipStream_t s) {
+                     hipStream_t s, const double* sub, double sigma) {
   if (M <= 0 || N <= 0) return;
   const int parts = (K + kchunk - 1) / kchunk;
   const long long cstride = (long long)M * N;
@@ -391,7 +394,7 @@ void gemm_f64_splitk(const double* A, long long lda, const double* B, long long 
   long long count = (long long)M * N;
   int blocks = (int)((count + 255) / 256);
   hipLaunchKernelGGL(k_sum_partials, dim3(blocks < 4096 ? blocks : 4096), dim3(256), 0, s,
-                     partials, parts, count, cstride, C);
+                     partials, parts, count, cstride, C, sub, sigma);
   (void)ldc;
 }
 

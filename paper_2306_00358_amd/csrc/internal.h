@@ -70,9 +70,11 @@ void gemm_f64_grouped(int blayout, const F64Item* d_items, const int* d_begin, i
 // Split-K FP64 GEMM for products with small M x N and long K: partial
 // products of K chunks go to `partials` (ceil(K/kchunk) * M * N doubles) and
 // are summed in a fixed order into the row-major M x N matrix C.
+// C = A B over K chunks of kchunk summed in order; with sub, C -= sigma * sub
+// (sub laid out like C)
 void gemm_f64_splitk(const double* A, long long lda, const double* B, long long ldb, int blayout,
                      double* C, long long ldc, int M, int N, int K, int kchunk, double* partials,
-                     hipStream_t s);
+                     hipStream_t s, const double* sub = nullptr, double sigma = 0.0);
 
 // Direct-to-LDS FP64 GEMM (gemm_lds.hip); returns false if the operands do
 // not meet its alignment / K-multiple requirements.  variant 0: 4 waves,
@@ -192,8 +194,8 @@ struct CholItem {
 void launch_chol_inv_batched(const CholItem* d_items, int count, int pmax, int pass, bool full,
                              hipStream_t s);
 bool topk_eigs(rocblas_handle blas, const double* M, int n, int p, int need, double tol,
-               int q_first, double* ws, double* W, double* Xout, int* dinfo, int* iters,
-               int* enough, double* resid, hipStream_t s);
+               int q_first, double* shift, int* nocheck, double* ws, double* W, double* Xout,
+               int* dinfo, int* iters, int* enough, double* resid, hipStream_t s);
 void launch_layout_u(const double* Ucan, int dx, int dn, void* U1, void* U3, bool out_f32,
                      hipStream_t s);
 void launch_norm(const unsigned long long* maxbits, const void* Tt, bool f32, int dn, int dy,
