@@ -8,7 +8,7 @@
 // fast, so iterating a block of p > D' vectors converges in a few sweeps at
 // the rate lambda_{p+1} / lambda_{D'} per sweep.
 //
-// One sweep:  Y = V M  (rows of V are the p basis vectors)
+// One sweep:  Y = V (M - sigma I)  (rows of V are the p basis vectors)
 //             V = orth(Y) by shifted Cholesky-QR (Fukaya et al., "Shifted
 //             Cholesky QR for computing the QR factorization of
 //             ill-conditioned matrices", SIAM J. Sci. Comput. 42 (2020)):
@@ -19,12 +19,17 @@
 //             one shifted pass leaves a basis too ill-conditioned for an
 //             unshifted Cholesky; a second shifted pass brings it within
 //             reach, and the third restores orthonormality to rounding.)
-//             Before a check all three passes run.  Between checks V only has to stay a
-//             well-conditioned basis of the same span: one pass after the
-//             first, which the device leaves out (R^-1 = I) when G is
+//             V = R^-T Y is a blocked triangular solve (k_trsm_rows).
+//             Before a check all three passes run.  Between checks V only
+//             has to stay a well-conditioned basis of the same span: one
+//             pass, then a second that the device reduces to R = I when G is
 //             already the identity to 1e-2 -- after the first pass it is
-//             typically so to 1e-7..1e-4, except in a solve's first sweep.
-// Check:      H = V (V M)^T, H = Z diag(theta) Z^T (rocSOLVER on p x p),
+//             typically so to 1e-7..1e-4, except in a solve's first sweep
+//             (and once no such check misses, only the first sweep after a
+//             check is checked).
+// Check:      H = V (V M)^T, H = Z diag(theta) Z^T (Householder reduction to
+//             tridiagonal form in one workgroup, then rocSOLVER's divide and
+//             conquer on the tridiagonal, which applies the reduction),
 //             Ritz vectors X = Z^T V, residuals |(Z^T Y)_i - theta_i X_i|.
 // Converged when the residuals of the `need` leading pairs are below
 // tol * theta_1; otherwise the sweeps continue from X.  The first check
@@ -477,6 +482,146 @@ void launch_chol_inv_batched(const CholItem* d_items, int count, int pmax, int p
                      full ? 1 : 0);
 }
 
+// Householder reduction of a small symmetric matrix to tridiagonal form in
+// one workgroup, for the Rayleigh-Ritz step (its tridiagonal eigenproblem
+// goes to rocSOLVER's divide and conquer).  H (p x p, symmetric, 3 <= p <=
+// 128) lives in registers: thread t = 8 i + q holds row i's entries in
+// columns q, q + 8, ..., so a matrix-vector product is 16 FMAs per thread and
+// a reduction over 8 neighbouring lanes.  For k = 0 .. p-3 the entries of row
+// k past the diagonal, x (the column, by symmetry), give v (v_0 = 1) and tau
+// with (I - tau v v^T) x = beta e_1, and the trailing block takes
+// A <- A - v w^T - w v^T, w = tau A v - (tau^2 / 2) (v^T A v) v (the standard
+// symmetric two-sided update).  The reflectors are kept in LDS; Q = H_0 H_1
+// ... H_{p-3} is then accumulated from the back, as Q^T in the same register
+// layout, and written over H column-major as the reduction matrix the
+// tridiagonal solver expects; d (p) and e (p - 1) receive the tridiagonal.
+// Every loop has a fixed trip count and every sum a fixed order.
+constexpr int kTrdThreads = 1024;
+
+__device__ __forceinline__ double trd_block_sum(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < kTrdThreads / 64; ++w) s += red[w];
+  __syncthreads();  // every thread has read red before it is written again
+  return s;
+}
+
+__device__ __forceinline__ double trd_sum8(double v) {
+  v += __shfl_xor(v, 1, 64);
+  v += __shfl_xor(v, 2, 64);
+  return v + __shfl_xor(v, 4, 64);
+}
+
+__global__ __launch_bounds__(kTrdThreads) void k_sytrd_small(double* __restrict__ H, int p,
+                                                             double* __restrict__ d,
+                                                             double* __restrict__ e) {
+  // reflector k at Vr[128 k + c], zero outside its columns k+1 .. p-1; the
+  // vectors of a step are likewise zero outside the trailing block, so the
+  // register loops below need no bounds tests
+  extern __shared__ double Vr[];
+  __shared__ double xs[128], vsa[2][128], wsa[128], taus[128], red[kTrdThreads / 64];
+  const int t = threadIdx.x, i = t >> 3, q = t & 7;
+  const bool own = i < p;
+  double a[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int c = q + 8 * r;
+    a[r] = (own && c < p) ? H[i * p + c] : 0.0;
+  }
+  if (t < 128) wsa[t] = 0.0;
+  for (int k = 0; k + 2 < p; ++k) {
+    const int o = k + 1;
+    double* vs = vsa[k & 1];
+    if (i == k) {  // row k publishes its entries
+#pragma unroll
+      for (int r = 0; r < 16; ++r) xs[q + 8 * r] = a[r];
+    }
+    __syncthreads();
+    const bool tail = t >= o && t < p;
+    const double xt = tail ? xs[t] : 0.0;
+    const double nrm2 = trd_block_sum(xt * xt, red);
+    const double x0 = xs[o];
+    double beta, tau, scale;
+    if (nrm2 == 0.0) {
+      beta = x0;
+      tau = 0.0;
+      scale = 0.0;
+    } else {
+      beta = -copysign(sqrt(nrm2), x0);
+      tau = (beta - x0) / beta;
+      scale = 1.0 / (x0 - beta);
+    }
+    if (t < 128) {
+      const double v = t == o ? 1.0 : (tail ? xt * scale : 0.0);
+      vs[t] = v;
+      Vr[128 * k + t] = v;
+    }
+    if (t == 0) {
+      taus[k] = tau;
+      e[k] = beta;
+      d[k] = xs[k];
+    }
+    __syncthreads();
+    // (tau A v)_i for the rows of the trailing block
+    const bool act = own && i >= o;
+    double acc = 0.0;
+    if (act) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc += a[r] * vs[q + 8 * r];
+    }
+    const double wraw = tau * trd_sum8(acc);
+    if (own && q == 0) wsa[i] = act ? wraw : 0.0;
+    // alpha = -tau/2 v^T w (the sum's barriers also publish wsa)
+    const double alpha = -0.5 * tau * trd_block_sum(act && q == 0 ? wraw * vs[i] : 0.0, red);
+    if (act) {
+      const double vi = vs[i], wi = wraw + alpha * vi;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int c = q + 8 * r;
+        a[r] -= vi * (wsa[c] + alpha * vs[c]) + wi * vs[c];
+      }
+    }
+  }
+  // the last 2 x 2 block
+  if (i == p - 2 || i == p - 1) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int c = q + 8 * r;
+      if (c == i) d[i] = a[r];
+      if (i == p - 1 && c == p - 2) e[p - 2] = a[r];
+    }
+  }
+  __syncthreads();
+  // Q from the back, held as Q^T: rows j >= k+1 of Q^T take
+  // -(tau Q^T v)_j v^T (v zero outside columns k+1 ..)
+#pragma unroll
+  for (int r = 0; r < 16; ++r) a[r] = (own && q + 8 * r == i) ? 1.0 : 0.0;
+  for (int k = p - 3; k >= 0; --k) {
+    const double* v = Vr + 128 * k;
+    const bool act = own && i > k;
+    double acc = 0.0;
+    if (act) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc += a[r] * v[q + 8 * r];
+    }
+    const double y = taus[k] * trd_sum8(acc);
+    if (act) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) a[r] -= y * v[q + 8 * r];
+    }
+  }
+  // Q column-major: H[c + j p] = Q[c][j] = Q^T[j][c]
+  if (own) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int c = q + 8 * r;
+      if (c < p) H[c + i * p] = a[r];
+    }
+  }
+}
+
 __global__ void k_symmetrize_small(double* H, int p) {
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < p * p; e += gridDim.x * blockDim.x) {
     const int i = e / p, j = e % p;
@@ -583,7 +728,7 @@ bool topk_eigs(rocblas_handle blas, const double* M, int n, int p, int need, dou
   double* G = part + partial_doubles(n, p);
   double* Rt = G + pp;
   double* H = Rt + pp;
-  double* E = H + pp;          // p (tridiagonal work for dsyevd)
+  double* E = H + pp;          // off-diagonal of the tridiagonal form (p - 1)
   double* res = E + pp;        // p
   int* fail = (int*)(res + p); // fail flag, then the count of checks that missed
   // a pass's Cholesky factor (p x p) at Rt and its row scaling (p) in the
@@ -600,7 +745,10 @@ bool topk_eigs(rocblas_handle blas, const double* M, int n, int p, int need, dou
            hipFuncSetAttribute((const void*)k_trsm_rows,
                                hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)(((size_t)128 * 128 + 128 * 16) * sizeof(double))) ==
-               hipSuccess;
+               hipSuccess &&
+           hipFuncSetAttribute((const void*)k_sytrd_small,
+                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)((size_t)128 * 128 * sizeof(double))) == hipSuccess;
   }();
   const size_t trsm_lds = ((size_t)p * p + (size_t)p * 16) * sizeof(double);
   if (!lds_set || p > 128 || p % 16 != 0) return false;
@@ -650,7 +798,11 @@ bool topk_eigs(rocblas_handle blas, const double* M, int n, int p, int need, dou
     vm(V, Y, 0.0);
     gemm_f64_splitk(V, n, Y, n, B_KCONTIG, H, p, p, p, n, kc, part, s);
     hipLaunchKernelGGL(k_symmetrize_small, dim3(16), dim3(256), 0, s, H, p);
-    if (rocsolver_dsyevd(blas, rocblas_evect_original, rocblas_fill_lower, p, H, p, W, E, dinfo) !=
+    // tridiagonal form and its reduction matrix in one workgroup, then
+    // divide and conquer
+    hipLaunchKernelGGL(k_sytrd_small, dim3(1), dim3(kTrdThreads),
+                       (size_t)128 * p * sizeof(double), s, H, p, W, E);
+    if (rocsolver_dstedc(blas, rocblas_evect_original, p, W, E, H, p, dinfo) !=
         rocblas_status_success)
       return false;
     // H now holds Z column-major: row i of Z^T is H[i*p .. i*p+p)
