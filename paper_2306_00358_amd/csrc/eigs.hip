@@ -498,16 +498,6 @@ void launch_chol_inv_batched(const CholItem* d_items, int count, int pmax, int p
 // Every loop has a fixed trip count and every sum a fixed order.
 constexpr int kTrdThreads = 1024;
 
-__device__ __forceinline__ double trd_block_sum(double v, double* red) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  double s = 0.0;
-  for (int w = 0; w < kTrdThreads / 64; ++w) s += red[w];
-  __syncthreads();  // every thread has read red before it is written again
-  return s;
-}
-
 __device__ __forceinline__ double trd_sum8(double v) {
   v += __shfl_xor(v, 1, 64);
   v += __shfl_xor(v, 2, 64);
@@ -521,7 +511,7 @@ __global__ __launch_bounds__(kTrdThreads) void k_sytrd_small(double* __restrict_
   // vectors of a step are likewise zero outside the trailing block, so the
   // register loops below need no bounds tests
   extern __shared__ double Vr[];
-  __shared__ double xs[128], vsa[2][128], wsa[128], taus[128], red[kTrdThreads / 64];
+  __shared__ double vsa[2][128], wsa[128], taus[128], red[kTrdThreads / 64];
   const int t = threadIdx.x, i = t >> 3, q = t & 7;
   const bool own = i < p;
   double a[16];
@@ -534,36 +524,45 @@ __global__ __launch_bounds__(kTrdThreads) void k_sytrd_small(double* __restrict_
   for (int k = 0; k + 2 < p; ++k) {
     const int o = k + 1;
     double* vs = vsa[k & 1];
-    if (i == k) {  // row k publishes its entries
+    if (i == k) {
+      // row k's eight owners (eight lanes of one wave) form the reflector
+      // from their own entries and publish it with tau, beta and d_k
+      double s2 = 0.0, x0 = 0.0, dk = 0.0;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) xs[q + 8 * r] = a[r];
+      for (int r = 0; r < 16; ++r) {
+        const int c = q + 8 * r;
+        s2 += (c >= o && c < p) ? a[r] * a[r] : 0.0;
+        x0 = c == o ? a[r] : x0;
+        dk = c == k ? a[r] : dk;
+      }
+      const double nrm2 = trd_sum8(s2);
+      x0 = trd_sum8(x0);  // one lane holds it, the others add zeros
+      dk = trd_sum8(dk);
+      double beta, tau, scale;
+      if (nrm2 == 0.0) {
+        beta = x0;
+        tau = 0.0;
+        scale = 0.0;
+      } else {
+        beta = -copysign(sqrt(nrm2), x0);
+        tau = (beta - x0) / beta;
+        scale = 1.0 / (x0 - beta);
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int c = q + 8 * r;
+        const double v = c == o ? 1.0 : ((c > o && c < p) ? a[r] * scale : 0.0);
+        vs[c] = v;
+        Vr[128 * k + c] = v;
+      }
+      if (q == 0) {
+        taus[k] = tau;
+        e[k] = beta;
+        d[k] = dk;
+      }
     }
     __syncthreads();
-    const bool tail = t >= o && t < p;
-    const double xt = tail ? xs[t] : 0.0;
-    const double nrm2 = trd_block_sum(xt * xt, red);
-    const double x0 = xs[o];
-    double beta, tau, scale;
-    if (nrm2 == 0.0) {
-      beta = x0;
-      tau = 0.0;
-      scale = 0.0;
-    } else {
-      beta = -copysign(sqrt(nrm2), x0);
-      tau = (beta - x0) / beta;
-      scale = 1.0 / (x0 - beta);
-    }
-    if (t < 128) {
-      const double v = t == o ? 1.0 : (tail ? xt * scale : 0.0);
-      vs[t] = v;
-      Vr[128 * k + t] = v;
-    }
-    if (t == 0) {
-      taus[k] = tau;
-      e[k] = beta;
-      d[k] = xs[k];
-    }
-    __syncthreads();
+    const double tau = taus[k];
     // (tau A v)_i for the rows of the trailing block
     const bool act = own && i >= o;
     double acc = 0.0;
@@ -573,8 +572,16 @@ __global__ __launch_bounds__(kTrdThreads) void k_sytrd_small(double* __restrict_
     }
     const double wraw = tau * trd_sum8(acc);
     if (own && q == 0) wsa[i] = act ? wraw : 0.0;
-    // alpha = -tau/2 v^T w (the sum's barriers also publish wsa)
-    const double alpha = -0.5 * tau * trd_block_sum(act && q == 0 ? wraw * vs[i] : 0.0, red);
+    // alpha = -tau/2 v^T w: per-wave partial sums, published with wsa by
+    // one barrier (the next write of red comes after the next step's first
+    // barrier, which every thread reaches only after reading these)
+    double pa = act && q == 0 ? wraw * vs[i] : 0.0;
+    for (int sh = 32; sh > 0; sh >>= 1) pa += __shfl_xor(pa, sh, 64);
+    if ((t & 63) == 0) red[t >> 6] = pa;
+    __syncthreads();
+    double vw = 0.0;
+    for (int w = 0; w < kTrdThreads / 64; ++w) vw += red[w];
+    const double alpha = -0.5 * tau * vw;
     if (act) {
       const double vi = vs[i], wi = wraw + alpha * vi;
 #pragma unroll
