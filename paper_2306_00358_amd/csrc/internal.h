@@ -88,6 +88,28 @@ bool gemm_f64_lds(const double* A, long long lda, const double* B, long long ldb
                   double* C, const OutMap& om, int M, int N, int K, unsigned long long* maxbits,
                   hipStream_t s, int tag, int variant);
 
+// Tile order of a launch over tm x tn output tiles.  Workgroups are handed
+// round-robin to the 8 XCDs, each with its own L2.  With group gm > 0 the
+// XCD that receives workgroup b takes a contiguous eighth of the tiles,
+// walked gm row panels at a time (all of a group's rows for one column
+// panel, then the next column panel), so that the workgroups resident on an
+// XCD share a few row panels of A and column panels of B.  gm = 0:
+// row-major order.
+__device__ __forceinline__ void tile_order(int tm, int tn, int b, int gm, int& im, int& in) {
+  if (gm <= 0) {
+    im = b / tn;
+    in = b - im * tn;
+    return;
+  }
+  const int T = tm * tn;
+  const int t = (T & 7) ? b : (b & 7) * (T >> 3) + (b >> 3);
+  const int g = t / (gm * tn);
+  const int rows = min(gm, tm - g * gm);
+  const int r = t - g * gm * tn;
+  im = g * gm + r % rows;
+  in = r / rows;
+}
+
 // ---- reduced-precision contractions (gemm_rp.hip) ----
 enum RpMode { RP_F32 = 0, RP_BF16X3 = 1 };
 enum RpOut { RP_OUT_F32 = 0, RP_OUT_SPLIT = 1, RP_OUT_F64 = 2 };
