@@ -53,7 +53,7 @@ DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}
 # FETCH_SIZE / WRITE_SIZE counter runs of `bench.py --kernel-probe` (scaled by
 # the readings of a 1 GiB copy); the summary and commands are under profiles/.
 # An entry is valid only for the kernel version it was measured on.
-TRAFFIC = {("fp64", 64): 9.648e10, ("fp32", 64): 5.090e10, ("bf16x3", 64): 3.022e10}
+TRAFFIC = {("fp64", 64): 9.648e10, ("fp32", 64): 3.866e10, ("bf16x3", 64): 3.022e10}
 
 
 def parse():
