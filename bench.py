@@ -648,7 +648,7 @@ def main():
             "tflops": tflops,
             # whole run: issued MFMA flops over run time x peak (eigensolver included)
             "run_frac_of_peak": issued * tflops / PEAKS[pu],
-            "eigh_share": phase_ms.get("eigh", 0.0) / (elapsed / args.steps * 1e3),
+            "eigh_share": phase_ms.get("eigh", 0.0) / (elapsed / runs * 1e3),
             "lnz_per_site": lnz,
             "rel_err_vs_fp64_oracle": abs(lnz - ref) / abs(ref) if ref is not None else None,
             "rel_err_vs_onsager": abs(lnz - ONSAGER_TC) / ONSAGER_TC,
