@@ -321,6 +321,24 @@ int hotrg_ctx_timings(hotrg_ctx* ctx, hotrg_phase_time* out, int cap);
 hotrg_status hotrg_environment(hotrg_ctx* ctx, int prec, const double* T, int dx, int dy,
                                double* M);
 
+/* Projector of a step (Sec. 2): the leading eigenpairs of the environment M
+ * (device, n x n row-major, symmetric positive semidefinite; not modified)
+ * by the step's FP64 eigensolver -- block subspace iteration with
+ * Rayleigh-Ritz when d_new is small against n (n >= 1024), else the dense
+ * solver -- and the step's truncation rule (`trunc`: hotrg_trunc; with
+ * HOTRG_TRUNC_MULTIPLET the cut moves down while the gap at it is at most
+ * degen_tol lambda_1).  U (device, n x d_new row-major) receives the
+ * eigenvectors of the d_new largest eigenvalues as columns, in descending
+ * order (signs as the solver returns them), columns from *kept on zero;
+ * spec (host, spec_len values, may be NULL when spec_len = 0) the spectrum
+ * lambda_m / lambda_1, descending; *kept (host) the columns kept; *trunc_err
+ * (host) 1 - sum_{m < kept} lambda_m / Tr M.  2 <= n, 1 <= d_new <= n.
+ * HOTRG_ERR_NUMERIC when the eigensolver does not converge.  Waits for the
+ * context's stream. */
+hotrg_status hotrg_projector(hotrg_ctx* ctx, const double* M, int n, int d_new, int trunc,
+                             double degen_tol, int spec_len, double* U, double* spec, int* kept,
+                             double* trunc_err);
+
 /* Coarse tensor: Tt[i,j,k,l] = sum U[a,b,i] T[b,j,d,c] T[a,c,e,l] U[e,d,k]
  * (Sec. 2), T (dx,dy,dx,dy), U (dx,dx,dn), Tt (dn,dy,dn,dy); *max_abs
  * (device, may be NULL) receives max|Tt|. */

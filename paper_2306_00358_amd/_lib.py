@@ -31,7 +31,7 @@ EXPORTS = [
     "hotrg_ctx_set_workers", "hotrg_submit", "hotrg_poll", "hotrg_wait", "hotrg_cancel",
     "hotrg_footprint", "hotrg_run_batch", "hotrg_ctx_sched_stats", "hotrg_thermo",
     "hotrg_release", "hotrg_coarse_noalloc", "hotrg_plan", "hotrg_run_grouped",
-    "hotrg_ctx_group_stats",
+    "hotrg_ctx_group_stats", "hotrg_projector",
 ]
 
 NOALLOC_SCRATCH_BYTES = 64 << 20  # HOTRG_NOALLOC_SCRATCH_BYTES
@@ -107,6 +107,8 @@ def lib():
     L.hotrg_environment.argtypes = [vp, c_int, vp, c_int, c_int, vp]
     L.hotrg_coarse.argtypes = [vp, c_int, vp, vp, c_int, c_int, c_int, vp, vp]
     L.hotrg_coarse_noalloc.argtypes = [vp, vp, vp, c_int, c_int, c_int, vp, vp]
+    L.hotrg_projector.argtypes = [vp, vp, c_int, c_int, c_int, c_double, c_int, vp,
+                                  POINTER(c_double), POINTER(c_int), POINTER(c_double)]
     L.hotrg_ctx_enable_timing.argtypes = [vp, c_int]
     L.hotrg_ctx_set_workers.argtypes = [vp, c_int]
     L.hotrg_submit.argtypes = [vp, POINTER(ModelParams), POINTER(Opts), POINTER(Result),
@@ -307,6 +309,21 @@ def hotrg_coarse(ctx, T, U, Tt, max_abs=None, prec="fp64"):
     _check(lib().hotrg_coarse(ctx.ptr, _prec(prec), c_void_p(T.data_ptr()), c_void_p(U.data_ptr()),
                               dx, dy, dn, c_void_p(Tt.data_ptr()),
                               c_void_p(max_abs.data_ptr()) if max_abs is not None else None))
+
+
+def hotrg_projector(ctx, M, U, d_new, trunc="plain", degen_tol=1e-10, spec_len=0):
+    """Projector on device buffers: M (n, n) float64 environment -> U (n, d_new)
+    float64, the eigenvectors of the d_new largest eigenvalues (columns past
+    the kept count zero).  Returns (kept, truncation error, spectrum list)."""
+    n = M.shape[0]
+    spec = (c_double * max(spec_len, 1))()
+    kept = c_int(0)
+    err = c_double(0.0)
+    _check(lib().hotrg_projector(ctx.ptr, c_void_p(M.data_ptr()), n, d_new, TRUNC[trunc],
+                                 degen_tol, spec_len, c_void_p(U.data_ptr()),
+                                 spec if spec_len else None, ctypes.byref(kept),
+                                 ctypes.byref(err)))
+    return kept.value, err.value, list(spec[:spec_len])
 
 
 def hotrg_coarse_noalloc(ctx, T, U, Tt, max_abs=None):

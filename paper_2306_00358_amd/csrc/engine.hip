@@ -110,6 +110,14 @@ struct hotrg_ctx {
   int open_phase = -1, m_step = 0, m_dx = 0, m_dy = 0, m_dn = 0;
 };
 
+// What an iterative eigensolve learnt, for the next solve of the same kind:
+// its n, the sweeps it is estimated to have needed, the shift of its sweeps
+// and whether its orthogonality checks stopped missing.
+struct EigHint {
+  int n = 0, sweeps = 0, nocheck = 0;
+  double shift = 0.0;
+};
+
 struct hotrg_state {
   int prec = HOTRG_FP64;
   int dx = 0, dy = 0, k = 0;
@@ -125,11 +133,9 @@ struct hotrg_state {
   Buf recs;            // device: kRec doubles per step
   Buf spec;            // device spectra, spec_cap doubles per step
   int rec_cap = 0, spec_len = 0;
-  // sweeps the last iterative eigensolve of each step parity needed, and its n
+  // what the last iterative eigensolve of each step parity learnt
   // ([parity + 2 * side])
-  int eig_sweeps[4] = {0, 0, 0, 0}, eig_n[4] = {0, 0, 0, 0};
-  double eig_shift[4] = {0.0, 0.0, 0.0, 0.0};
-  int eig_nocheck[4] = {0, 0, 0, 0};
+  EigHint eig[4];
   // precision schedule: first step allowed in reduced precision, and the
   // a-priori error bound of the steps run reduced so far
   int first_reduced = 1;
@@ -530,6 +536,60 @@ void reserve_records(hotrg_ctx* c, hotrg_state* st, int k, int spec_len) {
   }
 }
 
+// Block size of the iterative eigensolve for d_new leading pairs of an n x n
+// environment; whether it applies (else the dense solver runs).
+static bool eig_block(int n, int dn, int spec_len, int eig_mode, int* need_out, int* p_out) {
+  const int need = std::max(dn + 1, std::min(spec_len, n));
+  int p = std::min(128, std::max(2 * dn, need + 16));
+  p = (p + 15) / 16 * 16;
+  *need_out = need;
+  *p_out = p;
+  return eig_mode == HOTRG_EIG_AUTO && n >= 1024 && need + 16 <= p && p <= 128 && p * 4 <= n;
+}
+
+// Leading eigenpairs of the symmetric n x n matrix in Mb: eigenvalues
+// (ascending) into Wb, eigenvector rows into Xb (p rows, iterative) or over Mb
+// (n rows, dense); returns the rows and their count.  A non-converged dense
+// solve is folded into *sticky; an iterative one that does not converge falls
+// back to the dense solver.
+static const double* leading_eigs(hotrg_ctx* c, Buf& Mb, Buf& Wb, Buf& Xb, int n, int need, int p,
+                                  bool sub_ok, EigHint& h, int* inf, int* sticky, int* cols_out) {
+  ensure(c, Wb, (size_t)n * 8);
+  if (sub_ok) {
+    ensure(c, c->EW, topk_workspace_doubles(n, p) * 8);
+    ensure(c, Xb, (size_t)p * n * 8);
+    int iters = 0, enough = 0;
+    double resid = 0.0;
+    // solves of the same kind: start with one sweep more than the last one
+    // is estimated to have needed, at its shift
+    const int q_first = h.n == n ? h.sweeps + 1 : 3;
+    if (h.n != n) {
+      h.shift = 0.0;
+      h.nocheck = 0;
+    }
+    const bool ok = topk_eigs(c->blas, (const double*)Mb.p, n, p, need, 5e-14, q_first, &h.shift,
+                              &h.nocheck, (double*)c->EW.p, (double*)Wb.p, (double*)Xb.p,
+                              (int*)((char*)c->scal.p + 48), &iters, &enough, &resid, c->stream);
+    h.n = ok ? n : 0;
+    h.sweeps = enough;
+    c->last_eig_iters = ok ? iters : 0;
+    c->last_eig_resid = resid;
+    if (ok) {
+      *cols_out = p;
+      return (const double*)Xb.p;
+    }
+  }
+  ensure(c, c->E, (size_t)n * 8);
+  rocblas_status rs = rocsolver_dsyevd(c->blas, rocblas_evect_original, rocblas_fill_lower, n,
+                                       (double*)Mb.p, n, (double*)Wb.p, (double*)c->E.p, inf);
+  if (rs != rocblas_status_success)
+    fail(HOTRG_ERR_DEVICE, "rocsolver_dsyevd failed with status " + std::to_string((int)rs));
+  // a non-converged solve marks the caller's flag: later solves overwrite `inf`
+  launch_fold_info(inf, sticky, 0, c->stream);
+  *cols_out = n;
+  return (const double*)Mb.p;
+}
+
 void do_step(hotrg_ctx* c, hotrg_state* st, const hotrg_opts* o) {
   const int dx = st->dx, dy = st->dy;
   const int n = dx * dx;
@@ -579,50 +639,11 @@ void do_step(hotrg_ctx* c, hotrg_state* st, const hotrg_opts* o) {
   launch_trace((const double*)c->M.p, n, trace, c->stream);
   mark(c, HOTRG_PHASE_EIGH);
   // leading eigenpairs: block subspace iteration when D' is small against n
-  const int need = std::max(dn + 1, std::min(o->spec_len, n));
-  int p = std::min(128, std::max(2 * dn, need + 16));
-  p = (p + 15) / 16 * 16;
-  const bool sub_ok = o->eig == HOTRG_EIG_AUTO && n >= 1024 && need + 16 <= p && p <= 128 &&
-                      p * 4 <= n;
-  // eigenpairs of Mb into Wb (and Xb or Mb itself); returns the eigenvector
-  // rows and their count
+  int need = 0, p = 0;
+  const bool sub_ok = eig_block(n, dn, o->spec_len, o->eig, &need, &p);
   auto solve = [&](Buf& Mb, Buf& Wb, Buf& Xb, int side, int* inf, int* cols_out) {
-    ensure(c, Wb, (size_t)n * 8);
-    bool sub = sub_ok;
-    if (sub) {
-      ensure(c, c->EW, topk_workspace_doubles(n, p) * 8);
-      ensure(c, Xb, (size_t)p * n * 8);
-      int iters = 0, enough = 0;
-      double resid = 0.0;
-      // steps of equal parity see environments of the same kind: start with
-      // one sweep more than the last such solve is estimated to have needed
-      const int slot = (st->k & 1) + 2 * side;
-      const int q_first = st->eig_n[slot] == n ? st->eig_sweeps[slot] + 1 : 3;
-      if (st->eig_n[slot] != n) {
-        st->eig_shift[slot] = 0.0;
-        st->eig_nocheck[slot] = 0;
-      }
-      sub = topk_eigs(c->blas, (const double*)Mb.p, n, p, need, 5e-14, q_first,
-                      &st->eig_shift[slot], &st->eig_nocheck[slot], (double*)c->EW.p,
-                      (double*)Wb.p, (double*)Xb.p,
-                      (int*)((char*)c->scal.p + 48), &iters, &enough, &resid, c->stream);
-      st->eig_n[slot] = sub ? n : 0;
-      st->eig_sweeps[slot] = enough;
-      c->last_eig_iters = sub ? iters : 0;
-      c->last_eig_resid = resid;
-      if (sub) {
-        *cols_out = p;
-        return (const double*)Xb.p;
-      }
-    }
-    rocblas_status rs = rocsolver_dsyevd(c->blas, rocblas_evect_original, rocblas_fill_lower, n,
-                                         (double*)Mb.p, n, (double*)Wb.p, (double*)c->E.p, inf);
-    if (rs != rocblas_status_success)
-      fail(HOTRG_ERR_DEVICE, "rocsolver_dsyevd failed with status " + std::to_string((int)rs));
-    // a non-converged solve marks the state: later solves overwrite `inf`
-    launch_fold_info(inf, st_fail, 0, c->stream);
-    *cols_out = n;
-    return (const double*)Mb.p;
+    return leading_eigs(c, Mb, Wb, Xb, n, need, p, sub_ok, st->eig[(st->k & 1) + 2 * side], inf,
+                        st_fail, cols_out);
   };
   int cols = n;
   const double* evec = solve(c->M, c->W, c->Xr, 0, info, &cols);
@@ -1842,6 +1863,62 @@ hotrg_status hotrg_environment(hotrg_ctx* c, int prec, const double* T, int dx, 
       throw;
     }
     release_operands(c, &tmp);
+  });
+}
+
+hotrg_status hotrg_projector(hotrg_ctx* c, const double* M, int n, int dn, int trunc,
+                             double degen_tol, int spec_len, double* U, double* spec, int* kept,
+                             double* trunc_err) {
+  return guard([&] {
+    if (!c || !M || !U || !kept || !trunc_err) fail(HOTRG_ERR_INVALID, "NULL argument");
+    if (n < 2 || dn < 1 || dn > n) fail(HOTRG_ERR_INVALID, "need 2 <= n and 1 <= d_new <= n");
+    if ((long long)n * n > (1LL << 28)) fail(HOTRG_ERR_INVALID, "n too large");
+    if (spec_len < 0 || (spec_len > 0 && !spec))
+      fail(HOTRG_ERR_INVALID, "spec_len < 0 or spec NULL with spec_len > 0");
+    if (trunc != HOTRG_TRUNC_PLAIN && trunc != HOTRG_TRUNC_MULTIPLET)
+      fail(HOTRG_ERR_INVALID, "unknown truncation rule");
+    if (!(degen_tol >= 0.0)) fail(HOTRG_ERR_INVALID, "degen_tol must be >= 0");
+    HIPCHK(hipSetDevice(c->device));
+    ensure(c, c->scal, 64);
+    ensure(c, c->M, (size_t)n * n * 8);
+    HIPCHK(hipMemcpyAsync(c->M.p, M, (size_t)n * n * 8, hipMemcpyDeviceToDevice, c->stream));
+    launch_symmetrize((double*)c->M.p, n, c->stream);
+    double* trace = (double*)((char*)c->scal.p + 40);
+    int* info = (int*)((char*)c->scal.p + 8);
+    launch_trace((const double*)c->M.p, n, trace, c->stream);
+    int need = 0, p = 0;
+    const bool sub_ok = eig_block(n, dn, spec_len, HOTRG_EIG_AUTO, &need, &p);
+    // record (6 doubles), sticky flag, kept count, spectrum
+    Buf out;
+    ensure(c, out, (size_t)(8 + spec_len) * 8);
+    try {
+      double* rec = (double*)out.p;
+      int* sticky = (int*)(rec + 6);
+      int* kept_d = sticky + 1;
+      double* spec_d = spec_len ? rec + 8 : nullptr;
+      HIPCHK(hipMemsetAsync(sticky, 0, sizeof(int), c->stream));
+      EigHint h;  // a solve of its own
+      int cols = n;
+      const double* evec =
+          leading_eigs(c, c->M, c->W, c->Xr, n, need, p, sub_ok, h, info, sticky, &cols);
+      launch_spectrum((const double*)c->W.p, cols, n, dn, trunc, degen_tol, spec_len, trace,
+                      spec_d, rec, kept_d, c->stream);
+      launch_isometry(evec, cols, n, dn, kept_d, U, c->stream);
+      int hk[2] = {0, 0};
+      HIPCHK(hipMemcpyAsync(hk, sticky, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(hipMemcpyAsync(trunc_err, rec + 1, 8, hipMemcpyDeviceToHost, c->stream));
+      if (spec_len)
+        HIPCHK(hipMemcpyAsync(spec, spec_d, (size_t)spec_len * 8, hipMemcpyDeviceToHost,
+                              c->stream));
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipStreamSynchronize(c->stream));
+      if (hk[0] != 0) fail(HOTRG_ERR_NUMERIC, "eigensolver did not converge");
+      *kept = hk[1];
+    } catch (...) {
+      ctx_free(c, out);
+      throw;
+    }
+    ctx_free(c, out);
   });
 }
 

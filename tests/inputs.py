@@ -47,3 +47,23 @@ def serving_stream(n, seed):
             out.append(("potts", rng.uniform(0.8, 1.2), 0, 3,
                         int(rng.choice([8, 12, 16])), int(rng.integers(10, 25))))
     return out
+
+
+def graded_gram(n, rank, decay, seed):
+    """A seeded symmetric positive semidefinite n x n array G diag(w) G^T of
+    the given rank: G standard normal (n x rank), w = 10^(-decay i / rank)
+    (graded like a coarse-graining environment's spectrum)."""
+    rng = np.random.default_rng(seed)
+    G = rng.standard_normal((n, rank))
+    w = 10.0 ** (-decay * np.arange(rank) / rank)
+    return (G * w) @ G.T
+
+
+def orthogonal_with_spectrum(values, seed):
+    """Q diag(values) Q^T for a seeded orthogonal Q (QR of a standard normal
+    square array, signs fixed by R's diagonal)."""
+    n = len(values)
+    rng = np.random.default_rng(seed)
+    Q, R = np.linalg.qr(rng.standard_normal((n, n)))
+    Q = Q * np.sign(np.diag(R))
+    return (Q * np.asarray(values, dtype=np.float64)) @ Q.T

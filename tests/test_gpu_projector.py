@@ -1,0 +1,127 @@
+"""The step's projector (hotrg_projector: FP64 eigensolver, truncation rule
+and isometry of Sec. 2) against the oracle's projector (an SVD of M) on
+environments of three kinds: one from an oracle coarse-graining run (Ising at
+T_c, D = 32, n = 1024, block subspace iteration), graded synthetic ones
+(n = 2304 and 4096, blocks of 96 and 128 vectors; n = 576, the dense solver)
+and one with an exactly degenerate pair at the cut (multiplet rule).
+
+Compared: the normalised spectrum lambda_m / lambda_1 (1e-12), the kept count
+(exact), the truncation error (1e-12) and the projector's action on M,
+|(P - P_oracle) M| / |M| with P = U U^T, which is insensitive to the
+arbitrary basis of eigenvectors with tiny eigenvalues and to their signs
+(1e-11).  The columns of U are orthonormal to 1e-12.
+"""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import hotrg, tensors
+from tests.inputs import graded_gram, orthogonal_with_spectrum
+
+pytestmark = pytest.mark.gpu
+
+BETA_C = math.log(1 + math.sqrt(2)) / 2
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a GPU")
+    return torch
+
+
+def _ising_environment(d_cut, steps):
+    # the oracle's own coarse-graining: steps directional steps, then the
+    # environment of the next one
+    T = tensors.ising(BETA_C)
+    T = T / np.abs(T).max()
+    for _ in range(steps):
+        Tt, _, _, _, _ = hotrg.directional_step(T, d_cut)
+        T = hotrg.rotate(Tt)
+        T = T / np.abs(T).max()
+    return hotrg.environment(T)
+
+
+def _check(torch, ctx, M, d_new, trunc="plain", tau=1e-10, spec_len=None, label=""):
+    from paper_2306_00358_amd import hotrg_projector
+
+    n = M.shape[0]
+    spec_len = spec_len or min(n, d_new + 8)
+    Md = torch.from_numpy(np.ascontiguousarray(M)).to("cuda")
+    Ud = torch.empty((n, d_new), dtype=torch.float64, device="cuda")
+    say(label, "n", n, "d_new", d_new, trunc)
+    kept, err, spec = hotrg_projector(ctx, Md, Ud, d_new, trunc=trunc, degen_tol=tau,
+                                      spec_len=spec_len)
+    U = Ud.cpu().numpy()
+    Uo, s, d_o, kept_o = hotrg.projector(M, d_new, trunc, tau)
+    assert d_o == d_new
+    assert kept == kept_o, (kept, kept_o)
+    want_spec = s[:spec_len] / s[0]
+    d_spec = np.abs(np.asarray(spec) - want_spec).max()
+    d_err = abs(err - hotrg.truncation_error(s, kept_o))
+    P, Po = U @ U.T, Uo @ Uo.T
+    d_proj = np.abs((P - Po) @ M).max() / np.abs(M).max()
+    d_orth = np.abs(U[:, :kept].T @ U[:, :kept] - np.eye(kept)).max()
+    say("  kept", kept, "spectrum", d_spec, "trunc err", d_err, "projector", d_proj, "orth", d_orth)
+    assert d_spec <= 1e-12
+    assert d_err <= 1e-12
+    assert d_proj <= 1e-11
+    assert d_orth <= 1e-12
+    assert np.all(U[:, kept:] == 0.0)
+
+
+def test_projector_of_an_oracle_ising_environment(torch_cuda):
+    from paper_2306_00358_amd import Context
+
+    M = _ising_environment(32, 7)  # dims 32 x 32 from step 6 on: n = 1024
+    assert M.shape == (1024, 1024)
+    with Context(0) as ctx:
+        _check(torch_cuda, ctx, M, 32, spec_len=40, label="ising T_c step 8")
+
+
+@pytest.mark.parametrize("n, d_new, rank, decay, seed", [
+    (2304, 48, 320, 10.0, 11),   # block of 96 vectors
+    (4096, 64, 384, 12.0, 12),   # block of 128 vectors (the D = 64 shape)
+    (576, 24, 200, 9.0, 13),     # n < 1024: the dense solver
+])
+def test_projector_of_graded_environments(torch_cuda, n, d_new, rank, decay, seed):
+    from paper_2306_00358_amd import Context
+
+    M = graded_gram(n, rank, decay, seed)
+    with Context(0) as ctx:
+        _check(torch_cuda, ctx, M, d_new, spec_len=d_new + 16, label="graded")
+
+
+def test_projector_multiplet_cut_at_a_degenerate_pair(torch_cuda):
+    from paper_2306_00358_amd import Context
+
+    # lambda_32 = lambda_33 exactly: the multiplet rule keeps 31 (the plain
+    # rule would keep 32, whose 32nd vector is any unit vector of the pair's
+    # plane: no unique projector to compare)
+    vals = 10.0 ** (-np.arange(1024) / 40.0)
+    vals[32] = vals[31]
+    M = orthogonal_with_spectrum(vals, 14)
+    with Context(0) as ctx:
+        _check(torch_cuda, ctx, M, 32, trunc="multiplet", tau=1e-10, label="degenerate")
+
+
+def test_projector_rejects_bad_arguments(torch_cuda):
+    from paper_2306_00358_amd import Context, HotrgError, hotrg_projector
+
+    M = torch_cuda.eye(64, dtype=torch_cuda.float64, device="cuda")
+    U = torch_cuda.empty((64, 8), dtype=torch_cuda.float64, device="cuda")
+    with Context(0) as ctx:
+        with pytest.raises(HotrgError):
+            hotrg_projector(ctx, M, U, 65)
+        with pytest.raises(HotrgError):
+            hotrg_projector(ctx, M, U, 8, degen_tol=-1.0)
