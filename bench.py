@@ -349,8 +349,9 @@ def serve_errors(ctx, reqs, vals):
 def batch_record(args):
     """The 64-problem XY batch (FP32 contractions): in lockstep (grouped
     launches, one HIP graph per sweep; after one untimed batch that tunes the
-    grouped tiles) and on the worker pool (after a warm-up batch of the first
-    problems), each result of the lockstep run against the pool's."""
+    grouped tiles), on the worker pool (after a warm-up batch of the first
+    problems) and one problem after another on one stream; each result of the
+    lockstep run against the pool's."""
     import torch
 
     from paper_2306_00358_amd import Context, hotrg_run_batch, hotrg_run_grouped
@@ -382,6 +383,16 @@ def batch_record(args):
         torch.cuda.synchronize()
         dt_p = time.perf_counter() - t0
     log("batch, worker pool: %d problems in %.2f s" % (len(P), dt_p))
+    from paper_2306_00358_amd import hotrg_run
+
+    with Context(0) as ctx:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for p, o in zip(P, O):
+            hotrg_run(ctx, p, o)
+        torch.cuda.synchronize()
+        dt_s = time.perf_counter() - t0
+    log("batch, one problem after another: %d problems in %.2f s" % (len(P), dt_s))
     diff = [abs(a["lnz_per_site"] - b["lnz_per_site"]) / abs(b["lnz_per_site"])
             for a, b in zip(res_g, res_p) if a and b]
     stats = {k: s1[k] - s0[k] for k in s1}
@@ -393,7 +404,10 @@ def batch_record(args):
             "worker_pool": {"workers": args.workers, "steps_per_s": n_dir / dt_p,
                             "tflops": flops / dt_p / 1e12, "seconds": dt_p,
                             "failed": sum(1 for x in st_p if x != 0)},
+            "sequential": {"steps_per_s": n_dir / dt_s, "tflops": flops / dt_s / 1e12,
+                           "seconds": dt_s},
             "speedup_vs_worker_pool": dt_p / dt_g,
+            "speedup_vs_sequential": dt_s / dt_g,
             "max_rel_diff_vs_worker_pool": max(diff) if diff else None,
             "max_stated_error_bound": max(r["err_bound"] for r in res_g if r)}
 

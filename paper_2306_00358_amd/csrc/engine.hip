@@ -950,6 +950,7 @@ void group_sweep(hotrg_ctx* c, GRun& R, bool tune, std::vector<std::vector<long 
     for (int sw = 0; sw < kGroupSweepsPerRound; ++sw) {
       const bool full = sw == kGroupSweepsPerRound - 1;
       launch_f64_table(R.vm, B_NCONTIG, s);  // Y = V M
+      group_shift(R.steps, G, R.max_pn, s);  // Y -= sigma V
       pass(R.gramY, 0, full, R.apYT2);
       if (full) {
         pass(R.gramT2, 1, full, R.apT2Y);
@@ -1118,6 +1119,7 @@ void group_tables(hotrg_ctx* c, GRun& R, Buf& store, std::vector<std::vector<lon
     d.trace = (double*)((char*)g->scal.p + 8);
     d.kept = (int*)((char*)g->scal.p + 16);
     d.maxbits = (unsigned long long*)g->scal.p;
+    d.shift = (double*)((char*)g->scal.p + 64);
     d.recs = (double*)g->st->recs.p;
     d.spec = (double*)g->st->spec.p;
     d.acc = (double*)g->st->acc.p;
@@ -1366,7 +1368,9 @@ void run_grouped_impl(hotrg_ctx* c, int N, const hotrg_model_params* params,
         ensure(c, g.M, (size_t)(n * n) * 8);
         ensure(c, g.eig, (size_t)(5 * pn + 3 * pp + 2 * g.p + 16) * 8);
         ensure(c, g.U, (size_t)(n * D) * 8);
-        ensure(c, g.scal, 64);
+        ensure(c, g.scal, 128);
+        // sweep shifts of the two step parities (offset 64): none yet
+        HIPCHK(hipMemsetAsync((char*)g.scal.p + 64, 0, 16, c->stream));
         if (red) {
           const long long ldP = pad32(D * D), ldx = pad32(D), ldn = pad32(n);
           ensure(c, g.Tt, (size_t)(D * D * D * D) * 4);

@@ -199,7 +199,24 @@ __global__ void k_group_resid(const GroupStep* __restrict__ d, int last) {
     const bool ok = th1 > 0.0 && worst <= s.tol * th1;
     if (ok || last) s.ctl->iter = 0;
     if (!ok && last) s.ctl->fail = 1;
+    // the shift of the sweeps to come, and of the next solve of this parity
+    s.shift[s.ctl->k & 1] = 0.5 * fmax(s.W[0], 0.0);
   }
+}
+
+// Y <- Y - sigma V after a sweep's product Y = V M: the sweeps iterate with
+// M - sigma I (M positive semidefinite, unwanted eigenvalues in
+// [0, lambda_{p+1}]; sigma = theta_min / 2 <= lambda_p / 2), the
+// Rayleigh-Ritz products with M
+__global__ void k_group_shift(const GroupStep* __restrict__ d) {
+  const GroupStep& s = d[blockIdx.y];
+  if (!s.ctl->iter) return;
+  const double sg = s.shift[s.ctl->k & 1];
+  if (!(sg > 0.0)) return;
+  const long long count = (long long)s.p * s.n;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < count;
+       e += (long long)gridDim.x * blockDim.x)
+    s.Y[e] -= sg * s.V[e];
 }
 
 // continue from the Ritz vectors: V <- X while still iterating
@@ -355,6 +372,9 @@ void group_jacobi(const GroupStep* d, int count, int pmax, hipStream_t s) {
 }
 void group_resid(const GroupStep* d, int count, bool last, hipStream_t s) {
   hipLaunchKernelGGL(k_group_resid, dim3(count), dim3(256), 0, s, d, last ? 1 : 0);
+}
+void group_shift(const GroupStep* d, int count, long long max_pn, hipStream_t s) {
+  hipLaunchKernelGGL(k_group_shift, dim3(gblocks(max_pn), count), dim3(256), 0, s, d);
 }
 void group_restart(const GroupStep* d, int count, long long max_pn, hipStream_t s) {
   hipLaunchKernelGGL(k_group_restart, dim3(gblocks(max_pn), count), dim3(256), 0, s, d);

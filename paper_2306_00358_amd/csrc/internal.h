@@ -253,6 +253,7 @@ struct GroupStep {
   const void* Tt;
   int tt_f32;
   unsigned long long* maxbits;
+  double* shift;  // sweep shift per step parity (theta_min / 2 of the last Rayleigh-Ritz)
 };
 void group_begin(const GroupStep* d, int count, hipStream_t s);
 void group_seed(const GroupStep* d, int count, long long max_pn, hipStream_t s);
@@ -260,6 +261,7 @@ void group_symm_h(const GroupStep* d, int count, hipStream_t s);
 void group_jacobi(const GroupStep* d, int count, int pmax, hipStream_t s);
 void group_resid(const GroupStep* d, int count, bool last, hipStream_t s);
 void group_restart(const GroupStep* d, int count, long long max_pn, hipStream_t s);
+void group_shift(const GroupStep* d, int count, long long max_pn, hipStream_t s);
 // whole small environments (n <= 96, p = n rounded up to even) by Jacobi
 void group_dense(const GroupStep* d, int count, int pmax, hipStream_t s);
 void group_spectrum(const GroupStep* d, int count, hipStream_t s);
