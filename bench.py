@@ -9,7 +9,7 @@ built on the host inside the call, so `ms_per_step` is milliseconds per
 directional coarse-graining steps per second over the timed runs.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec fp64|fp32|bf16x3]
-                    [--no-cpu-baseline] [--no-compare] [--no-batch] [--no-serve]
+                    [--no-cpu-baseline] [--no-compare] [--no-batch] [--no-serve] [--no-cases]
                     [--kernel-probe]
 
 Prints one JSON line.  The headline (`value`) uses --prec contractions
@@ -69,6 +69,8 @@ def parse():
                     help="skip the FP32 / split-BF16 runs of the same workload")
     ap.add_argument("--no-batch", action="store_true", help="skip the batch sub-record")
     ap.add_argument("--no-serve", action="store_true", help="skip the serve sub-record")
+    ap.add_argument("--no-cases", action="store_true",
+                    help="skip the D_cut = 8 and D_cut = 32 sub-records (for profiling one workload)")
     ap.add_argument("--cpu-baseline-child", type=int, default=0, metavar="THREADS",
                     help=argparse.SUPPRESS)
     ap.add_argument("--batch", action="store_true",
@@ -704,8 +706,9 @@ def main():
     }
     out["run_frac_of_peak"] = head["run_frac_of_peak"]
     out["eigh_share"] = head["eigh_share"]
-    out["small_case"] = small_case(ctx)
-    out["mid_case"] = mid_case(ctx)
+    if not args.no_cases:
+        out["small_case"] = small_case(ctx)
+        out["mid_case"] = mid_case(ctx)
     if not args.no_compare:
         # the same workload with reduced-precision contractions (eigensolver
         # and log-norm stay FP64)
