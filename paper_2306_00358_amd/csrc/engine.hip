@@ -553,7 +553,8 @@ static bool eig_block(int n, int dn, int spec_len, int eig_mode, int* need_out, 
 // solve is folded into *sticky; an iterative one that does not converge falls
 // back to the dense solver.
 static const double* leading_eigs(hotrg_ctx* c, Buf& Mb, Buf& Wb, Buf& Xb, int n, int need, int p,
-                                  bool sub_ok, EigHint& h, int* inf, int* sticky, int* cols_out) {
+                                  bool sub_ok, EigHint& h, int* inf, int* sticky, int* cols_out,
+                                  double tol = 5e-14) {
   ensure(c, Wb, (size_t)n * 8);
   if (sub_ok) {
     ensure(c, c->EW, topk_workspace_doubles(n, p) * 8);
@@ -567,7 +568,7 @@ static const double* leading_eigs(hotrg_ctx* c, Buf& Mb, Buf& Wb, Buf& Xb, int n
       h.shift = 0.0;
       h.nocheck = 0;
     }
-    const bool ok = topk_eigs(c->blas, (const double*)Mb.p, n, p, need, 5e-14, q_first, &h.shift,
+    const bool ok = topk_eigs(c->blas, (const double*)Mb.p, n, p, need, tol, q_first, &h.shift,
                               &h.nocheck, (double*)c->EW.p, (double*)Wb.p, (double*)Xb.p,
                               (int*)((char*)c->scal.p + 48), &iters, &enough, &resid, c->stream);
     h.n = ok ? n : 0;
@@ -643,7 +644,7 @@ void do_step(hotrg_ctx* c, hotrg_state* st, const hotrg_opts* o) {
   const bool sub_ok = eig_block(n, dn, o->spec_len, o->eig, &need, &p);
   auto solve = [&](Buf& Mb, Buf& Wb, Buf& Xb, int side, int* inf, int* cols_out) {
     return leading_eigs(c, Mb, Wb, Xb, n, need, p, sub_ok, st->eig[(st->k & 1) + 2 * side], inf,
-                        st_fail, cols_out);
+                        st_fail, cols_out, eig_tolerance(sp));
   };
   int cols = n;
   const double* evec = solve(c->M, c->W, c->Xr, 0, info, &cols);
@@ -827,7 +828,6 @@ namespace {
 
 constexpr int kGroupRounds = 9;          // Rayleigh-Ritz checks per step
 constexpr int kGroupSweepsPerRound = 4;  // subspace sweeps before each check
-constexpr double kGroupTol = 5e-14;      // residual tolerance (as do_step's solver)
 
 struct GProb {
   int idx = 0;          // position in the caller's arrays
@@ -1104,7 +1104,7 @@ void group_tables(hotrg_ctx* c, GRun& R, Buf& store, std::vector<std::vector<lon
     d.spec_len = g->st->spec_len;
     d.K = g->o.n_steps;
     d.tau = g->o.degen_tol;
-    d.tol = kGroupTol;
+    d.tol = eig_tolerance(R.sp);  // residual tolerance (as do_step's solver)
     d.M = (const double*)g->M.p;
     d.V = e;
     d.Y = e + pn;

@@ -31,6 +31,17 @@ namespace hotrg {
 // relative ln Z/N error a reduced step k may add, times 2^k (by precision)
 constexpr double kErrPerStep[3] = {0.0, 2.0e-5, 1.0e-4};
 
+// Relative residual at which the block eigensolver of a step in precision p
+// stops.  The environment of a reduced step carries rounding of relative size
+// ~u_p (FP32 2^-24, split BF16 ~2^-17), which already moves its eigenvectors
+// by ~u_p / gap; a residual below 2^-10 u_p adds a thousandth of that, so
+// the sweeps past it buy nothing the step's result can show.  FP64 steps
+// iterate to 5e-14.
+constexpr double kEnvRounding[3] = {0.0, 5.9604644775390625e-08, 7.62939453125e-06};
+inline double eig_tolerance(int p) {
+  return std::max(5e-14, std::ldexp(kEnvRounding[p], -10));
+}
+
 // Whole-step contraction rates on one MI355X (TFLOP/s of algorithmic flops,
 // measured at D_cut = 64) used to compare precisions at admission.
 constexpr double kStepRate[3] = {65.0, 120.0, 270.0};
