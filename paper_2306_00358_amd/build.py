@@ -19,7 +19,7 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.path.join(ROCM, "bin", "hipcc")
 
 SOURCES = ["engine.hip", "eigs.hip", "gemm.hip", "gemm_lds.hip", "gemm_rp.hip", "group.hip", "kernels.hip",
-           "models.cpp", "noalloc.hip", "sched.cpp"]
+           "models.cpp", "noalloc.hip", "sched.cpp", "stedc.hip"]
 
 CFLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -484,7 +484,7 @@ void launch_chol_inv_batched(const CholItem* d_items, int count, int pmax, int p
 
 // Householder reduction of a small symmetric matrix to tridiagonal form in
 // one workgroup, for the Rayleigh-Ritz step (its tridiagonal eigenproblem
-// goes to rocSOLVER's divide and conquer).  H (p x p, symmetric, 3 <= p <=
+// goes to the divide and conquer of k_stedc_small).  H (p x p, symmetric, 3 <= p <=
 // 128) lives in registers: thread t = 8 i + q holds row i's entries in
 // columns q, q + 8, ..., so a matrix-vector product is 16 FMAs per thread and
 // a reduction over 8 neighbouring lanes.  For k = 0 .. p-3 the entries of row
@@ -805,16 +805,16 @@ bool topk_eigs(rocblas_handle blas, const double* M, int n, int p, int need, dou
     vm(V, Y, 0.0);
     gemm_f64_splitk(V, n, Y, n, B_KCONTIG, H, p, p, p, n, kc, part, s);
     hipLaunchKernelGGL(k_symmetrize_small, dim3(16), dim3(256), 0, s, H, p);
-    // tridiagonal form and its reduction matrix in one workgroup, then
-    // divide and conquer
+    // tridiagonal form and its reduction matrix (H = Q^T, row-major) in one
+    // workgroup, then divide and conquer on the tridiagonal in another
+    // (Z^T into Rt, eigenvalues over its diagonal in W)
     hipLaunchKernelGGL(k_sytrd_small, dim3(1), dim3(kTrdThreads),
                        (size_t)128 * p * sizeof(double), s, H, p, W, E);
-    if (rocsolver_dstedc(blas, rocblas_evect_original, p, W, E, H, p, dinfo) !=
-        rocblas_status_success)
-      return false;
-    // H now holds Z column-major: row i of Z^T is H[i*p .. i*p+p)
-    gemm_f64(H, p, V, n, B_NCONTIG, Xout, out_rowmajor(n), p, n, p, nullptr, s);
-    gemm_f64(H, p, Y, n, B_NCONTIG, Yx, out_rowmajor(n), p, n, p, nullptr, s);
+    if (!tridiag_eig_small(W, E, p, W, Rt, dinfo, s)) return false;
+    // Ritz vectors of H as rows: G = Z^T Q^T
+    gemm_f64(Rt, p, H, p, B_NCONTIG, G, out_rowmajor(p), p, p, p, nullptr, s);
+    gemm_f64(G, p, V, n, B_NCONTIG, Xout, out_rowmajor(n), p, n, p, nullptr, s);
+    gemm_f64(G, p, Y, n, B_NCONTIG, Yx, out_rowmajor(n), p, n, p, nullptr, s);
     hipLaunchKernelGGL(k_ritz_residual, dim3(p), dim3(256), 0, s, Yx, Xout, W, n, res);
     int hinfo[3] = {0, 0, 0};
     (void)hipMemcpyAsync(th.data(), W, p * sizeof(double), hipMemcpyDeviceToHost, s);

@@ -176,6 +176,13 @@ void launch_prep_rp(const void* src, bool src_f32, bool rotate, int dx, int dy,
 void launch_layout_u_rp(const double* Ucan, int dx, int dn, int mode, void* u1hi, void* u1lo,
                         void* u3hi, void* u3lo, long long ldx, long long ldn, hipStream_t s);
 
+// All eigenpairs of the symmetric tridiagonal (d, e), n <= 128, in one
+// workgroup (divide and conquer): eigenvalues ascending into W (which may be
+// d), eigenvectors as the rows of Zt (n x n); *info = 1 if a result is not
+// finite.  False when the launch fails.
+bool tridiag_eig_small(const double* d, const double* e, int n, double* W, double* Zt, int* info,
+                       hipStream_t s);
+
 // ---- small kernels (kernels.hip) ----
 void launch_maxabs(const void* x, long long n, bool is_f32, unsigned long long* maxbits, hipStream_t s);
 void launch_init_acc(const unsigned long long* maxbits, double* acc, hipStream_t s);
