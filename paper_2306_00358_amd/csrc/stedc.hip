@@ -72,6 +72,21 @@ __device__ __forceinline__ double dc_prod8(double v) {
   return v * dc_dpp<0x141>(v);
 }
 
+// 1 / x: v_rcp_f64 refined by two Newton steps
+__device__ __forceinline__ double dc_rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+__device__ __forceinline__ double dc_max8(double v) {
+  v = fmax(v, dc_dpp<0xB1>(v));
+  v = fmax(v, dc_dpp<0x4E>(v));
+  return fmax(v, dc_dpp<0x141>(v));
+}
+
 // node k of tree level D over n indices: [(k n) >> D, ((k + 1) n) >> D)
 struct DcMerge {
   int a, b, c;
@@ -129,45 +144,38 @@ __global__ __launch_bounds__(kDcThreads) void k_stedc_small(const double* din, c
       }
     }
     __syncthreads();
-    // poles of each merge in ascending order (ties by column); the first
-    // index of a merge also forms |z|, rho and tol
-    if (t < n) {
-      const DcMerge g = dc_merge_of(t, D, n);
-      if (g.real) {
-        const double lv = lam[t];
-        int r = 0;
-        for (int i0 = g.a; i0 < g.b; i0 += 8) {
-          double lb[8];
-#pragma unroll
-          for (int q = 0; q < 8; ++q) lb[q] = lam[min(i0 + q, g.b - 1)];
-#pragma unroll
-          for (int q = 0; q < 8; ++q)
-            r += (i0 + q < g.b && (lb[q] < lv || (lb[q] == lv && i0 + q < t))) ? 1 : 0;
+    // poles of each merge in ascending order (ties by column), 8 lanes per
+    // index; the first index of a merge also forms |z|, rho and tol
+    {
+      const int e8 = t >> 3, u = t & 7;
+      const DcMerge g = dc_merge_of(e8 < n ? e8 : 0, D, n);
+      if (e8 < n && g.real) {
+        const double lv = lam[e8];
+        double r = 0.0;
+        for (int i = g.a + u; i < g.b; i += 8) {
+          const double li = lam[i];
+          r += (li < lv || (li == lv && i < e8)) ? 1.0 : 0.0;
         }
-        sd[g.a + r] = lv;
-        sz[g.a + r] = zv[t];
-        scol[g.a + r] = t - g.a;
-        if (t == g.a) {
+        const int rk = (int)dc_sum8(r);
+        if (u == 0) {
+          sd[g.a + rk] = lv;
+          sz[g.a + rk] = zv[e8];
+          scol[g.a + rk] = e8 - g.a;
+        }
+        if (e8 == g.a) {
           double s2 = 0.0, dmax = 0.0;
-          for (int i0 = g.a; i0 < g.b; i0 += 8) {
-            double zb[8], lb[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-              const int i = min(i0 + q, g.b - 1);
-              zb[q] = zv[i];
-              lb[q] = lam[i];
-            }
-#pragma unroll
-            for (int q = 0; q < 8; ++q)
-              if (i0 + q < g.b) {
-                s2 += zb[q] * zb[q];
-                dmax = fmax(dmax, fabs(lb[q]));
-              }
+          for (int i = g.a + u; i < g.b; i += 8) {
+            s2 += zv[i] * zv[i];
+            dmax = fmax(dmax, fabs(lam[i]));
           }
-          const double rho = fabs(e[g.c - 1]) * s2;
-          mrho[g.a] = rho;
-          msc[g.a] = s2 > 0.0 ? 1.0 / sqrt(s2) : 0.0;
-          mtol[g.a] = 8.0 * eps * fmax(dmax, rho);
+          s2 = dc_sum8(s2);
+          dmax = dc_max8(dmax);
+          if (u == 0) {
+            const double rho = fabs(e[g.c - 1]) * s2;
+            mrho[g.a] = rho;
+            msc[g.a] = s2 > 0.0 ? 1.0 / sqrt(s2) : 0.0;
+            mtol[g.a] = 8.0 * eps * fmax(dmax, rho);
+          }
         }
       }
     }
@@ -287,40 +295,14 @@ __global__ __launch_bounds__(kDcThreads) void k_stedc_small(const double* din, c
       const int j = gs - a;
       if (gs < n && g.real && j < K) {
         const double rho = mrho[a], rinv = 1.0 / rho;
-        int o;
-        double lo, hi;
-        if (j < K - 1) {
-          const double gap = dh[a + j + 1] - dh[a + j];
-          const double mid = 0.5 * gap;
-          double f = 0.0;
-          for (int i = u; i < K; i += 8) {
-            const double dl = (dh[a + i] - dh[a + j]) - mid;
-            f += zh[a + i] * zh[a + i] / dl;
-          }
-          f = dc_sum8(f) + rinv;
-          if (f >= 0.0) {
-            o = j;
-            lo = 0.0;
-            hi = mid;
-          } else {
-            o = j + 1;
-            lo = -(gap - mid);
-            hi = 0.0;
-          }
-        } else {
-          double s2 = 0.0;
-          for (int i = u; i < K; i += 8) s2 += zh[a + i] * zh[a + i];
-          o = K - 1;
-          lo = 0.0;
-          hi = rho * dc_sum8(s2);
-        }
-        const double org = dh[a + o];
-        double tv = 0.5 * (lo + hi);
-        for (int it = 0; it < 80; ++it) {
-          double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0;
+        // sums of the secular function and of its slope over the poles left
+        // (i <= j) and right of the root at tv, in the frame of origin pole org
+        double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0;
+        auto sums = [&](double org, double tv) {
+          psi = dpsi = phi = dphi = 0.0;
           for (int i = u; i < K; i += 8) {
             const double zq = zh[a + i];
-            const double r = zq / ((dh[a + i] - org) - tv);
+            const double r = zq * dc_rcp((dh[a + i] - org) - tv);
             if (i <= j) {
               psi += zq * r;
               dpsi += r * r;
@@ -333,6 +315,40 @@ __global__ __launch_bounds__(kDcThreads) void k_stedc_small(const double* din, c
           dpsi = dc_sum8(dpsi);
           phi = dc_sum8(phi);
           dphi = dc_sum8(dphi);
+        };
+        int o;
+        double lo, hi, tv;
+        bool have = false;
+        if (j < K - 1) {
+          // the sign at the midpoint of (d_j, d_j+1) picks the nearer pole as
+          // origin; the sums there start the iteration
+          const double gap = dh[a + j + 1] - dh[a + j];
+          const double mid = 0.5 * gap;
+          sums(dh[a + j], mid);
+          have = true;
+          if (rinv + psi + phi >= 0.0) {
+            o = j;
+            lo = 0.0;
+            hi = mid;
+            tv = mid;
+          } else {
+            o = j + 1;
+            lo = -(gap - mid);
+            hi = 0.0;
+            tv = lo;
+          }
+        } else {
+          double s2 = 0.0;
+          for (int i = u; i < K; i += 8) s2 += zh[a + i] * zh[a + i];
+          o = K - 1;
+          lo = 0.0;
+          hi = rho * dc_sum8(s2);
+          tv = 0.5 * hi;
+        }
+        const double org = dh[a + o];
+        for (int it = 0; it < 80; ++it) {
+          if (!have) sums(org, tv);
+          have = false;
           const double f = rinv + psi + phi;
           if (!(fabs(f) < INFINITY)) {
             if (u == 0) bad = 1;
