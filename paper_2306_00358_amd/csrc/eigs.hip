@@ -498,10 +498,21 @@ void launch_chol_inv_batched(const CholItem* d_items, int count, int pmax, int p
 // Every loop has a fixed trip count and every sum a fixed order.
 constexpr int kTrdThreads = 1024;
 
+// another lane of the same 8-lane group (DPP: quad_perm [1,0,3,2],
+// quad_perm [2,3,0,1], row_half_mirror); every lane of the group is active
+template <int kCtrl>
+__device__ __forceinline__ double trd_dpp(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, kCtrl, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), kCtrl, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// sum over the 8-lane group, the same bits in every lane
 __device__ __forceinline__ double trd_sum8(double v) {
-  v += __shfl_xor(v, 1, 64);
-  v += __shfl_xor(v, 2, 64);
-  return v + __shfl_xor(v, 4, 64);
+  v += trd_dpp<0xB1>(v);
+  v += trd_dpp<0x4E>(v);
+  return v + trd_dpp<0x141>(v);
 }
 
 __global__ __launch_bounds__(kTrdThreads) void k_sytrd_small(double* __restrict__ H, int p,
@@ -511,7 +522,7 @@ __global__ __launch_bounds__(kTrdThreads) void k_sytrd_small(double* __restrict_
   // vectors of a step are likewise zero outside the trailing block, so the
   // register loops below need no bounds tests
   extern __shared__ double Vr[];
-  __shared__ double vsa[2][128], wsa[128], taus[128], red[kTrdThreads / 64];
+  __shared__ double vsa[2][128], wsa[128], wvs[128], taus[128];
   const int t = threadIdx.x, i = t >> 3, q = t & 7;
   const bool own = i < p;
   double a[16];
@@ -520,7 +531,7 @@ __global__ __launch_bounds__(kTrdThreads) void k_sytrd_small(double* __restrict_
     const int c = q + 8 * r;
     a[r] = (own && c < p) ? H[i * p + c] : 0.0;
   }
-  if (t < 128) wsa[t] = 0.0;
+  if (t < 128) wsa[t] = wvs[t] = 0.0;
   for (int k = 0; k + 2 < p; ++k) {
     const int o = k + 1;
     double* vs = vsa[k & 1];
@@ -571,17 +582,17 @@ __global__ __launch_bounds__(kTrdThreads) void k_sytrd_small(double* __restrict_
       for (int r = 0; r < 16; ++r) acc += a[r] * vs[q + 8 * r];
     }
     const double wraw = tau * trd_sum8(acc);
-    if (own && q == 0) wsa[i] = act ? wraw : 0.0;
-    // alpha = -tau/2 v^T w: per-wave partial sums, published with wsa by
-    // one barrier (the next write of red comes after the next step's first
-    // barrier, which every thread reaches only after reading these)
-    double pa = act && q == 0 ? wraw * vs[i] : 0.0;
-    for (int sh = 32; sh > 0; sh >>= 1) pa += __shfl_xor(pa, sh, 64);
-    if ((t & 63) == 0) red[t >> 6] = pa;
+    if (own && q == 0) {
+      wsa[i] = act ? wraw : 0.0;
+      wvs[i] = act ? wraw * vs[i] : 0.0;
+    }
     __syncthreads();
-    double vw = 0.0;
-    for (int w = 0; w < kTrdThreads / 64; ++w) vw += red[w];
-    const double alpha = -0.5 * tau * vw;
+    // alpha = -tau/2 v^T w: every 8-lane group sums the rows' products w_i v_i
+    // over its rows q + 8 r (together all p) -- the same bits everywhere
+    double pv = 0.0;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) pv += wvs[q + 8 * r];
+    const double alpha = -0.5 * tau * trd_sum8(pv);
     if (act) {
       const double vi = vs[i], wi = wraw + alpha * vi;
 #pragma unroll
