@@ -200,9 +200,13 @@ __device__ __forceinline__ void chol_inv_body(const double* __restrict__ G, int 
       for (int r = 0; r < 8; ++r) {
         const double d = L[r][r];
         ok = ok && d > 0.0;
-        const double rd = sqrt(d > 0.0 ? d : 1.0);
-        inv[r] = 1.0 / rd;
-        L[r][r] = rd;
+        // 1 / sqrt(d) from v_rsq_f64 and two Newton steps; sqrt(d) = d / sqrt(d)
+        const double dd = d > 0.0 ? d : 1.0;
+        double y = __builtin_amdgcn_rsq(dd);
+        y = fma(y, fma(-0.5 * dd * y, y, 0.5), y);
+        y = fma(y, fma(-0.5 * dd * y, y, 0.5), y);
+        inv[r] = y;
+        L[r][r] = dd * y;
 #pragma unroll
         for (int c = r + 1; c < 8; ++c) L[r][c] *= inv[r];
 #pragma unroll
