@@ -91,16 +91,9 @@ __global__ void k_seed_block(double* V, long long count, unsigned long long seed
 // LDS for coalesced stores.  *fail is set if a pivot is not positive.
 constexpr int kCholThreads = 256;
 
-//
-// With Rout the kernel stops after the factorisation and writes the factor R
-// of the matrix factored (p x p, row-major, zeros below the diagonal) to
-// Rout and the row scaling D^-1 to Rout + p * p (ones without `scale`);
-// RinvT is not touched.  Q = R^-T D^-1 Y then comes from k_trsm_rows.
 __device__ __forceinline__ void chol_inv_body(const double* __restrict__ G, int p,
                                               double shift_rel, int scale, double identity_tol,
-                                              double* __restrict__ RinvT, int* fail,
-                                              int* missed = nullptr,
-                                              double* __restrict__ Rout = nullptr) {
+                                              double* __restrict__ RinvT, int* fail) {
   extern __shared__ double lds[];
   double* R = lds;             // p * p: R (upper, zeros below), later X^T
   double* P = R + p * p;       // 2 x 8 x 128 published rows
@@ -133,12 +126,9 @@ __device__ __forceinline__ void chol_inv_body(const double* __restrict__ G, int 
     double mx = 0.0;
     for (int i = 0; i < kCholThreads; ++i) mx = fmax(mx, dev[i]);
     if (mx <= identity_tol) {  // uniform: every thread reduced the same values
-      double* out = Rout ? Rout : RinvT;
-      for (int e = t; e < p * p; e += kCholThreads) out[e] = (e / p == e % p) ? 1.0 : 0.0;
-      if (Rout && t < p) Rout[p * p + t] = 1.0;
+      for (int e = t; e < p * p; e += kCholThreads) RinvT[e] = (e / p == e % p) ? 1.0 : 0.0;
       return;
     }
-    if (missed && t == 0) *missed += 1;  // the check found a real factorisation to do
   }
   for (int e = t; e < p * p; e += kCholThreads) R[e] = 0.0;
   // diagonal: the owners publish it
@@ -268,13 +258,6 @@ __device__ __forceinline__ void chol_inv_body(const double* __restrict__ G, int 
       }
     }
   }
-  if (Rout) {
-    // every block's rows of R were written before the barrier that opened
-    // its trailing update
-    for (int e = t; e < p * p; e += kCholThreads) Rout[e] = R[e];
-    if (t < p) Rout[p * p + t] = dsc[t];
-    return;
-  }
   // X = I in registers
 #pragma unroll
   for (int a = 0; a < 8; ++a)
@@ -357,19 +340,194 @@ __device__ __forceinline__ void chol_inv_body(const double* __restrict__ G, int 
   for (int e = t; e < p * p; e += kCholThreads) RinvT[e] = R[e];
 }
 
-__global__ __launch_bounds__(kCholThreads) void k_chol_inv(const double* __restrict__ G, int p,
-                                                           double shift_rel, int scale,
-                                                           double identity_tol,
-                                                           double* __restrict__ RinvT,
-                                                           int* fail, int* missed,
-                                                           double* __restrict__ Rout) {
-  chol_inv_body(G, p, shift_rel, scale, identity_tol, RinvT, fail, missed, Rout);
+
+// Factor-only Cholesky of a sweep's Gram matrix (Q = R^-T D^-1 Y then comes
+// from k_trsm_rows): R with R^T R = D^-1 G D^-1 + s I (`scale`; D = diag(G)^1/2) or
+// G + s I, s = shift_rel * trace of the matrix factored, into Rout (p x p
+// row-major, zeros below the diagonal) and D^-1 (ones without `scale`) into
+// Rout + p * p; with identity_tol > 0 and G the identity to within it, R = I.
+// One workgroup of 1024 threads as a 32 x 32 grid; thread (ty, tx) keeps the
+// elements (ty + 32a, tx + 32b), a, b < 4, in registers (p <= 128, a multiple
+// of 16; indices past p are clamped and never published).  Blocks of 8
+// columns: the owners of the block's 8 rows publish them in LDS; every thread
+// the first wave factors the 8 x 8 diagonal block, one element per lane (1/sqrt
+// of a pivot from v_rsq_f64 and two Newton steps), into LDS; after a second barrier
+// thread c < p forms column c of the block's rows of R, into LDS (8 doubles
+// per column) and Rout; after a third every thread takes the rank-8 update.  Only the current block lives in LDS, so four waves per SIMD
+// fit with their register tiles.  *fail is set if a pivot is not positive.
+constexpr int kCholFThreads = 1024;
+
+__global__ __launch_bounds__(kCholFThreads) void k_chol_factor(const double* __restrict__ G, int p,
+                                                               double shift_rel, int scale,
+                                                               double identity_tol,
+                                                               double* __restrict__ Rout,
+                                                               int* fail, int* missed) {
+  __shared__ double Pb[8 * 128];                 // the block's rows of the working matrix
+  __shared__ __align__(16) double Rb[128 * 8];   // the block's rows of R, by column
+  __shared__ double dg[128], dsc[128], red[kCholFThreads / 64], Ls[64], Li[8];
+  __shared__ int bad;
+  const int t = threadIdx.x, tx = t & 31, ty = t >> 5;
+  const int pm = p - 1;
+  double A[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int i = min(ty + 32 * a, pm), k = min(tx + 32 * b, pm);
+      A[a][b] = G[min(i, k) * p + max(i, k)];  // upper part, mirrored
+    }
+  if (identity_tol > 0.0) {
+    double d = 0.0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int i = ty + 32 * a, k = tx + 32 * b;
+        if (i < p && k < p) d = fmax(d, fabs(A[a][b] - (i == k ? 1.0 : 0.0)));
+      }
+    for (int o = 32; o > 0; o >>= 1) d = fmax(d, __shfl_xor(d, o, 64));
+    if ((t & 63) == 0) red[t >> 6] = d;
+    __syncthreads();
+    double mx = 0.0;
+    for (int w = 0; w < kCholFThreads / 64; ++w) mx = fmax(mx, red[w]);
+    if (mx <= identity_tol) {  // uniform: every thread reduced the same values
+      for (int e = t; e < p * p; e += kCholFThreads) Rout[e] = (e / p == e % p) ? 1.0 : 0.0;
+      if (t < p) Rout[p * p + t] = 1.0;
+      return;
+    }
+    if (missed && t == 0) *missed += 1;  // the check found a real factorisation to do
+  }
+  if (tx == ty) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+      if (ty + 32 * a < p) dg[ty + 32 * a] = A[a][a];
+  }
+  if (t == 0) bad = 0;
+  __syncthreads();
+  if (t < 128) dsc[t] = (scale && t < p) ? 1.0 / sqrt(dg[t]) : 1.0;
+  // trace of the matrix factored, every thread summing in the same order
+  double tr = 0.0;
+  if (scale)
+    tr = (double)p;
+  else
+    for (int i = 0; i < p; ++i) tr += dg[i];
+  __syncthreads();
+  if (scale) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const double dr = dsc[min(ty + 32 * a, pm)];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) A[a][b] *= dr * dsc[min(tx + 32 * b, pm)];
+    }
+  }
+  const double shift = shift_rel * tr;
+  if (tx == ty) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a) A[a][a] += shift;
+  }
+
+  const int nblk = p >> 3;
+  for (int J = 0; J < nblk; ++J) {
+    const int j0 = 8 * J, aj = j0 >> 5, tj = j0 & 31;
+    if (ty >= tj && ty < tj + 8) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+        if (a == aj) {
+#pragma unroll
+          for (int b = 0; b < 4; ++b) Pb[(ty - tj) * 128 + tx + 32 * b] = A[a][b];
+        }
+    }
+    __syncthreads();
+    if (t < 64) {
+      // the 8 x 8 diagonal block, L[r][c] (c >= r) -> R[j0+r][j0+c], one
+      // element per lane of the first wave (lane 8r + c), right-looking
+      const int r0 = t >> 3, c0 = t & 7;
+      double x = c0 >= r0 ? Pb[r0 * 128 + j0 + c0] : 0.0;
+      bool ok = true;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const double d = __shfl(x, 9 * r, 64);
+        ok = ok && d > 0.0;
+        const double dd = d > 0.0 ? d : 1.0;
+        double y = __builtin_amdgcn_rsq(dd);
+        y = fma(y, fma(-0.5 * dd * y, y, 0.5), y);
+        y = fma(y, fma(-0.5 * dd * y, y, 0.5), y);
+        if (r0 == r) x = c0 == r ? dd * y : (c0 > r ? x * y : x);
+        if (t == 9 * r) Li[r] = y;
+        const double lc = __shfl(x, 8 * r + c0, 64);  // L[r][c0]
+        const double lr = __shfl(x, 8 * r + r0, 64);  // L[r][r0]
+        if (r0 > r && c0 >= r0) x -= lr * lc;
+      }
+      Ls[t] = x;
+      if (t == 0 && !ok) bad = 1;
+    }
+    __syncthreads();
+    if (t < p) {
+      // column t of the block's rows of R: forward substitution past the
+      // block, the factor itself inside it, zeros before it
+      double v[8];
+      if (t >= j0 + 8) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          double w = Pb[r * 128 + t];
+#pragma unroll
+          for (int m = 0; m < r; ++m) w -= Ls[m * 8 + r] * v[m];
+          v[r] = w * Li[r];
+        }
+      } else {
+        const int cc = t - j0;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) v[r] = cc >= 0 ? Ls[r * 8 + min(max(cc, 0), 7)] : 0.0;
+      }
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        if (t >= j0) Rb[t * 8 + r] = v[r];
+        Rout[(j0 + r) * p + t] = v[r];
+      }
+    }
+    __syncthreads();
+    if (bad) {
+      if (t == 0) *fail = 1;
+      return;  // uniform: every thread read the same flag after the barrier
+    }
+    // rank-8 update; register rows / columns wholly before j0 + 8 are
+    // finished and skipped (a uniform test), the others take it even where
+    // an element is finished -- nobody reads those again
+#pragma unroll
+    for (int h = 0; h < 8; h += 4) {  // two rank-4 halves keep the operands few
+      double Ri[4][4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        if (32 * a + 31 < j0 + 8) continue;
+        const int i = min(ty + 32 * a, pm);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Ri[a][r] = Rb[i * 8 + h + r];
+      }
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        if (32 * b + 31 < j0 + 8) continue;
+        const int k = min(tx + 32 * b, pm);
+        double Rk[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Rk[r] = Rb[k * 8 + h + r];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          if (32 * a + 31 < j0 + 8) continue;
+          double v = A[a][b];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) v -= Ri[a][r] * Rk[r];
+          A[a][b] = v;
+        }
+      }
+    }
+  }
+  if (t < p) Rout[p * p + t] = dsc[t];
 }
 
 // Q = R^-T D^-1 Y for the rows of Y (p x n, row-major): with L = R^T (lower
 // triangular), L Q = D^-1 Y is solved by blocks of 16 rows,
 //   Q_b = L_bb^-1 (D_b^-1 Y_b - sum_{a<b} L_ba Q_a),
-// where R and D^-1 are the output of k_chol_inv with Rout (R at Rf, D^-1 at
+// where R and D^-1 are the output of k_chol_factor (R at Rf, D^-1 at
 // Rf + p * p).  One workgroup per 64 columns; each of its 4 waves owns 16
 // columns and keeps their Q blocks in registers: in the accumulator layout of
 // v_mfma_f64_16x16x4f64 (lane j + 16 l holds rows l + 4 v of column j) value
@@ -756,15 +914,11 @@ bool topk_eigs(rocblas_handle blas, const double* M, int n, int p, int need, dou
   // a pass's Cholesky factor (p x p) at Rt and its row scaling (p) in the
   // first p entries of H, which only the Rayleigh-Ritz step uses
   double* Rf = Rt;
-  const size_t lds = ((size_t)p * p + 2048) * sizeof(double);
   const double u = std::ldexp(1.0, -53);
   const double shift_rel = 11.0 * ((double)n * p + (double)p * (p + 1)) * u;
 
   static bool lds_set = [] {
-    return hipFuncSetAttribute((const void*)k_chol_inv, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)(((size_t)128 * 128 + 2048) * sizeof(double))) ==
-               hipSuccess &&
-           hipFuncSetAttribute((const void*)k_trsm_rows,
+    return hipFuncSetAttribute((const void*)k_trsm_rows,
                                hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)(((size_t)128 * 128 + 128 * 16) * sizeof(double))) ==
                hipSuccess &&
@@ -787,9 +941,9 @@ bool topk_eigs(rocblas_handle blas, const double* M, int n, int p, int need, dou
     const int last = full ? 2 : (check ? 1 : 0);
     for (int pass = 0; pass <= last; ++pass) {
       gemm_f64_splitk(src, n, src, n, B_KCONTIG, G, p, p, p, n, kc, part, s);
-      hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(kCholThreads), lds, s, G, p,
+      hipLaunchKernelGGL(k_chol_factor, dim3(1), dim3(kCholFThreads), 0, s, G, p,
                          pass < 2 ? shift_rel : 0.0, pass < 2 ? 1 : 0,
-                         (pass == 0 || full) ? 0.0 : 1e-2, Rt, fail, fail + 1, Rf);
+                         (pass == 0 || full) ? 0.0 : 1e-2, Rf, fail, fail + 1);
       double* dst = (pass == last) ? Vout : (src == T2 ? Y : T2);
       if (dst == src) dst = (src == Y) ? T2 : Y;
       hipLaunchKernelGGL(k_trsm_rows, dim3((n + kTrsmCols - 1) / kTrsmCols), dim3(256), trsm_lds,
