@@ -311,6 +311,16 @@ typedef struct {
 hotrg_status hotrg_ctx_enable_timing(hotrg_ctx* ctx, int on);
 int hotrg_ctx_timings(hotrg_ctx* ctx, hotrg_phase_time* out, int cap);
 
+/* ---- eigensolver diagnostic ----------------------------------------------
+ * The context's last solve for the leading eigenpairs of an environment
+ * (Sec. 2; by the last step of hotrg_step / hotrg_run or by
+ * hotrg_projector): *sweeps = the block subspace sweeps it took and *resid =
+ * the largest relative Ritz residual of the pairs it needed, or *sweeps = 0
+ * when the solve was dense (rocSOLVER dsyevd, including a fallback after a
+ * block solve that did not converge).  Host pointers, either may be NULL;
+ * HOTRG_ERR_INVALID for a NULL ctx. */
+hotrg_status hotrg_ctx_last_eig(hotrg_ctx* ctx, int* sweeps, double* resid);
+
 /* ---- primitive contractions on caller device buffers (same kernels) -----
  * All pointers are device pointers of FP64 arrays, row-major; `prec`
  * selects the arithmetic of the contractions (inputs are rounded to it,

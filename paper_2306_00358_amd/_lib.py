@@ -31,7 +31,7 @@ EXPORTS = [
     "hotrg_ctx_set_workers", "hotrg_submit", "hotrg_poll", "hotrg_wait", "hotrg_cancel",
     "hotrg_footprint", "hotrg_run_batch", "hotrg_ctx_sched_stats", "hotrg_thermo",
     "hotrg_release", "hotrg_coarse_noalloc", "hotrg_plan", "hotrg_run_grouped",
-    "hotrg_ctx_group_stats", "hotrg_projector",
+    "hotrg_ctx_group_stats", "hotrg_projector", "hotrg_ctx_last_eig",
 ]
 
 NOALLOC_SCRATCH_BYTES = 64 << 20  # HOTRG_NOALLOC_SCRATCH_BYTES
@@ -110,6 +110,7 @@ def lib():
     L.hotrg_projector.argtypes = [vp, vp, c_int, c_int, c_int, c_double, c_int, vp,
                                   POINTER(c_double), POINTER(c_int), POINTER(c_double)]
     L.hotrg_ctx_enable_timing.argtypes = [vp, c_int]
+    L.hotrg_ctx_last_eig.argtypes = [vp, POINTER(c_int), POINTER(c_double)]
     L.hotrg_ctx_set_workers.argtypes = [vp, c_int]
     L.hotrg_submit.argtypes = [vp, POINTER(ModelParams), POINTER(Opts), POINTER(Result),
                                POINTER(ctypes.c_uint64)]
@@ -219,6 +220,13 @@ class Context:
 
     def enable_timing(self, on=True):
         _check(lib().hotrg_ctx_enable_timing(self.ptr, 1 if on else 0))
+
+    def last_eig(self):
+        """(sweeps, resid) of the context's last leading-eigenpair solve;
+        sweeps = 0 for a dense one."""
+        sw, rs = c_int(0), c_double(0.0)
+        _check(lib().hotrg_ctx_last_eig(self.ptr, byref(sw), byref(rs)))
+        return sw.value, rs.value
 
     def timings(self, cap=1 << 16):
         """Per-phase records since the last call: list of dicts with keys

@@ -581,6 +581,7 @@ static const double* leading_eigs(hotrg_ctx* c, Buf& Mb, Buf& Wb, Buf& Xb, int n
     }
   }
   ensure(c, c->E, (size_t)n * 8);
+  c->last_eig_iters = 0;  // dense
   rocblas_status rs = rocsolver_dsyevd(c->blas, rocblas_evect_original, rocblas_fill_lower, n,
                                        (double*)Mb.p, n, (double*)Wb.p, (double*)c->E.p, inf);
   if (rs != rocblas_status_success)
@@ -1802,6 +1803,14 @@ hotrg_status hotrg_ctx_enable_timing(hotrg_ctx* c, int on) {
   return guard([&] {
     if (!c) fail(HOTRG_ERR_INVALID, "ctx is NULL");
     c->timing = on != 0;
+  });
+}
+
+hotrg_status hotrg_ctx_last_eig(hotrg_ctx* c, int* sweeps, double* resid) {
+  return guard([&] {
+    if (!c) fail(HOTRG_ERR_INVALID, "ctx is NULL");
+    if (sweeps) *sweeps = c->last_eig_iters;
+    if (resid) *resid = c->last_eig_resid;
   });
 }
 

@@ -2,8 +2,10 @@
 and isometry of Sec. 2) against the oracle's projector (an SVD of M) on
 environments of three kinds: one from an oracle coarse-graining run (Ising at
 T_c, D = 32, n = 1024, block subspace iteration), graded synthetic ones
-(n = 2304 and 4096, blocks of 96 and 128 vectors; n = 576, the dense solver)
-and one with an exactly degenerate pair at the cut (multiplet rule).
+(n = 2304 and 4096, blocks of 96 and 128 vectors; n = 576, the dense solver),
+ones with exactly equal groups of eigenvalues all through the block (the
+deflation of the Rayleigh-Ritz divide and conquer) and one with an exactly
+degenerate pair at the cut (multiplet rule).
 
 Compared: the normalised spectrum lambda_m / lambda_1 (1e-12), the kept count
 (exact), the truncation error (1e-12) and the projector's action on M,
@@ -52,7 +54,8 @@ def _ising_environment(d_cut, steps):
     return hotrg.environment(T)
 
 
-def _check(torch, ctx, M, d_new, trunc="plain", tau=1e-10, spec_len=None, label=""):
+def _check(torch, ctx, M, d_new, trunc="plain", tau=1e-10, spec_len=None, label="",
+           iterative=None):
     from paper_2306_00358_amd import hotrg_projector
 
     n = M.shape[0]
@@ -63,6 +66,13 @@ def _check(torch, ctx, M, d_new, trunc="plain", tau=1e-10, spec_len=None, label=
     kept, err, spec = hotrg_projector(ctx, Md, Ud, d_new, trunc=trunc, degen_tol=tau,
                                       spec_len=spec_len)
     U = Ud.cpu().numpy()
+    sweeps, resid = ctx.last_eig()
+    say("  block sweeps", sweeps, "resid", resid)
+    if iterative is not None:
+        # the path the case is meant for ran: the block solver (and its
+        # Rayleigh-Ritz divide and conquer) converged, or the dense solver
+        assert (sweeps > 0) == iterative, sweeps
+        assert not iterative or resid <= 5e-14
     Uo, s, d_o, kept_o = hotrg.projector(M, d_new, trunc, tau)
     assert d_o == d_new
     assert kept == kept_o, (kept, kept_o)
@@ -86,7 +96,7 @@ def test_projector_of_an_oracle_ising_environment(torch_cuda):
     M = _ising_environment(32, 7)  # dims 32 x 32 from step 6 on: n = 1024
     assert M.shape == (1024, 1024)
     with Context(0) as ctx:
-        _check(torch_cuda, ctx, M, 32, spec_len=40, label="ising T_c step 8")
+        _check(torch_cuda, ctx, M, 32, spec_len=40, label="ising T_c step 8", iterative=True)
 
 
 @pytest.mark.parametrize("n, d_new, rank, decay, seed", [
@@ -99,7 +109,8 @@ def test_projector_of_graded_environments(torch_cuda, n, d_new, rank, decay, see
 
     M = graded_gram(n, rank, decay, seed)
     with Context(0) as ctx:
-        _check(torch_cuda, ctx, M, d_new, spec_len=d_new + 16, label="graded")
+        _check(torch_cuda, ctx, M, d_new, spec_len=d_new + 16, label="graded",
+               iterative=n >= 1024)
 
 
 def test_projector_multiplet_cut_at_a_degenerate_pair(torch_cuda):
@@ -113,6 +124,27 @@ def test_projector_multiplet_cut_at_a_degenerate_pair(torch_cuda):
     M = orthogonal_with_spectrum(vals, 14)
     with Context(0) as ctx:
         _check(torch_cuda, ctx, M, 32, trunc="multiplet", tau=1e-10, label="degenerate")
+
+
+@pytest.mark.parametrize("n, d_new, group, seed", [
+    (2304, 48, 4, 15),   # quadruplets through a block of 96 vectors
+    (4096, 64, 2, 16),   # pairs through a block of 128 vectors (the D = 64 shape)
+])
+def test_projector_with_exact_multiplets_inside_the_block(torch_cuda, n, d_new, group, seed):
+    from paper_2306_00358_amd import Context
+
+    # eigenvalues in exactly equal groups (as the coarse-grained tensors'
+    # symmetries make them) all through the Rayleigh-Ritz block: its
+    # tridiagonal form splits and the divide and conquer deflates equal
+    # poles; the cut falls between two groups, so the projector is unique
+    vals = 10.0 ** (-np.arange(n) / 60.0)
+    for g in range(0, 2 * d_new + 32, group):
+        vals[g:g + group] = vals[g]
+    assert vals[d_new - 1] != vals[d_new]
+    M = orthogonal_with_spectrum(vals, seed)
+    with Context(0) as ctx:
+        _check(torch_cuda, ctx, M, d_new, spec_len=d_new + 16, label="multiplets",
+               iterative=True)
 
 
 def test_projector_rejects_bad_arguments(torch_cuda):
