@@ -307,38 +307,103 @@ __device__ __forceinline__ void st_rp(void* hi, void* lo, long long i, float v, 
   }
 }
 
-__global__ void k_prep_rp(const void* src, bool src_f32, bool rotate, int dx, int dy,
-                          const unsigned long long* maxbits, float* Tn, int mode, RpOps ops,
-                          long long ldP, long long ldx) {
+// One pass of the operand preparation: element (l, u, r, d) of the tensor
+// (dims n = (dx, dy, dx, dy)) is read at sum idx * sst, scaled by 1 / max|T~|,
+// rounded and written at sum idx * dst (and at sum idx * tst into the FP32
+// copy Tn when Tn is given).  The dims ta (unit source stride) and tb (unit
+// destination stride, or another one when that is ta) are tiled 32 x 32;
+// blockIdx.y / z run over the other two.  With different unit-stride dims the
+// tile passes through LDS, so reads run along ta and writes along tb, both
+// coalesced; otherwise both run along ta directly.
+struct PrepPass {
+  long long sst[4], dst[4], tst[4];
+  int n[4];
+  int ta, tb, o0, o1;
+};
+
+__global__ __launch_bounds__(256) void k_prep_rp_pass(const void* src, bool src_f32, PrepPass P,
+                                                      const unsigned long long* maxbits,
+                                                      void* hi, void* lo, int mode, float* Tn) {
+  __shared__ float tile[32][33];
   const double inv = 1.0 / __longlong_as_double((long long)*maxbits);
-  const long long total = (long long)dx * dy * dx * dy;
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
-       e += (long long)gridDim.x * blockDim.x) {
-    long long q = e;
-    const int d = (int)(q % dy); q /= dy;
-    const int r = (int)(q % dx); q /= dx;
-    const int u = (int)(q % dy); q /= dy;
-    const int l = (int)q;
-    const long long si = rotate ? (((long long)u * dx + l) * dy + d) * dx + r : e;
-    const float v = (float)(ld_any(src, si, src_f32) * inv);
-    Tn[e] = v;
-    // OT rows (l,u), K (r,d)
-    st_rp(ops.hi[0], ops.lo[0], ((long long)l * dy + u) * ldP + (long long)r * dy + d, v, mode);
-    // OX rows (l,d), K (u,r)
-    st_rp(ops.hi[1], ops.lo[1], ((long long)l * dy + d) * ldP + (long long)u * dx + r, v, mode);
-    // OC1: element (row (j,d,c), k b) = T[b,j,d,c]: here b=l, j=u, d=r, c=d
-    st_rp(ops.hi[2], ops.lo[2], (((long long)u * dx + r) * dy + d) * ldx + l, v, mode);
-    // OC2: element (row (l,e), k (a,c)) = T[a,c,e,l]: a=l, c=u, e=r, l=d
-    st_rp(ops.hi[3], ops.lo[3], ((long long)d * dx + r) * ldP + (long long)l * dy + u, v, mode);
+  const int na = P.n[P.ta], nb = P.n[P.tb];
+  const int tiles_a = (na + 31) / 32;
+  const int a0 = (blockIdx.x % tiles_a) * 32, b0 = (blockIdx.x / tiles_a) * 32;
+  const long long sb = blockIdx.y * P.sst[P.o0] + blockIdx.z * P.sst[P.o1];
+  const long long db = blockIdx.y * P.dst[P.o0] + blockIdx.z * P.dst[P.o1];
+  const long long tb = blockIdx.y * P.tst[P.o0] + blockIdx.z * P.tst[P.o1];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const bool direct = P.dst[P.ta] == 1;
+  for (int k = ty; k < 32; k += 8) {
+    const int a = a0 + tx, b = b0 + k;
+    float v = 0.0f;
+    if (a < na && b < nb) {
+      v = (float)(ld_any(src, sb + a * P.sst[P.ta] + b * P.sst[P.tb], src_f32) * inv);
+      if (direct) {
+        st_rp(hi, lo, db + a * P.dst[P.ta] + b * P.dst[P.tb], v, mode);
+        if (Tn) Tn[tb + a * P.tst[P.ta] + b * P.tst[P.tb]] = v;
+      }
+    }
+    tile[k][tx] = v;
+  }
+  if (direct) return;  // uniform
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) {
+    const int b = b0 + tx, a = a0 + k;
+    if (a < na && b < nb) {
+      const float v = tile[tx][k];
+      st_rp(hi, lo, db + a * P.dst[P.ta] + b * P.dst[P.tb], v, mode);
+      if (Tn) Tn[tb + a * P.tst[P.ta] + b * P.tst[P.tb]] = v;
+    }
   }
 }
 
 void launch_prep_rp(const void* src, bool src_f32, bool rotate, int dx, int dy,
                     const unsigned long long* maxbits, float* Tn, int mode, const RpOps& ops,
                     long long ldP, long long ldx, hipStream_t s) {
-  const long long total = (long long)dx * dy * dx * dy;
-  hipLaunchKernelGGL(k_prep_rp, dim3(nblocks(total, 256)), dim3(256), 0, s, src, src_f32, rotate,
-                     dx, dy, maxbits, Tn, mode, ops, ldP, ldx);
+  // logical index order (l, u, r, d), dims (dx, dy, dx, dy); the source is
+  // T~ itself or, rotated, T~[u, l, d, r]
+  const long long X = dx, Y = dy;
+  const long long src_rot[4] = {Y * X, X * Y * X, 1, X};
+  const long long src_nat[4] = {Y * X * Y, X * Y, Y, 1};
+  const long long* sst = rotate ? src_rot : src_nat;
+  const long long nat[4] = {Y * X * Y, X * Y, Y, 1};
+  // OT rows (l,u), K (r,d); OX rows (l,d), K (u,r); OC1 rows (u,r,d), K l;
+  // OC2 rows (d,r), K (l,u)
+  const long long dsts[4][4] = {{Y * ldP, ldP, Y, 1},
+                                {Y * ldP, X, 1, ldP},
+                                {1, X * Y * ldx, Y * ldx, ldx},
+                                {Y, 1, ldP, X * ldP}};
+  for (int o = 0; o < 4; ++o) {
+    PrepPass P{};
+    for (int i = 0; i < 4; ++i) {
+      P.sst[i] = sst[i];
+      P.dst[i] = dsts[o][i];
+      P.tst[i] = nat[i];
+    }
+    P.n[0] = dx;
+    P.n[1] = dy;
+    P.n[2] = dx;
+    P.n[3] = dy;
+    int ta = 0, tb = -1;
+    for (int i = 0; i < 4; ++i)
+      if (sst[i] == 1) ta = i;
+    for (int i = 0; i < 4; ++i)
+      if (dsts[o][i] == 1 && i != ta) tb = i;
+    if (tb < 0) tb = ta == 3 ? 2 : 3;  // same unit-stride dim: any other one
+    int rest[2], nr = 0;
+    for (int i = 0; i < 4; ++i)
+      if (i != ta && i != tb) rest[nr++] = i;
+    P.ta = ta;
+    P.tb = tb;
+    P.o0 = rest[0];
+    P.o1 = rest[1];
+    const dim3 grid((unsigned)(((P.n[ta] + 31) / 32) * ((P.n[tb] + 31) / 32)),
+                    (unsigned)P.n[rest[0]], (unsigned)P.n[rest[1]]);
+    // the FP32 copy goes with OT, whose order it shares
+    hipLaunchKernelGGL(k_prep_rp_pass, grid, dim3(256), 0, s, src, src_f32, P, maxbits,
+                       ops.hi[o], ops.lo[o], mode, o == 0 ? Tn : nullptr);
+  }
 }
 
 __global__ void k_layout_u_rp(const double* Ucan, int dx, int dn, int mode, void* u1hi,
