@@ -65,34 +65,98 @@ void launch_init_acc(const unsigned long long* maxbits, double* acc, hipStream_t
 // ------------------------------------------------------------- operands --
 // Destination tensor T[l,u,r,d] of dims (dx,dy,dx,dy).  With `rotate`, the
 // source has dims (dy,dx,dy,dx) and T[l,u,r,d] = src[u,l,d,r].
-__global__ void k_prep(const void* src, bool src_f32, bool rotate, int dx, int dy,
-                       const unsigned long long* maxbits, void* Tn, void* Xt, void* Tp,
-                       bool out_f32) {
+// One pass of an operand preparation: element (l, u, r, d) of the tensor
+// (dims n = (dx, dy, dx, dy)) is read at sum idx * sst, scaled by 1 / max|T~|
+// and written at sum idx * dst (and at sum idx * tst into an FP32 copy when
+// one is given).  The dims ta (unit source stride) and tb (unit destination
+// stride, or another one when that is ta) are tiled 32 x 32; blockIdx.y / z
+// run over the other two.  With different unit-stride dims the tile passes
+// through LDS, so reads run along ta and writes along tb, both coalesced;
+// otherwise both run along ta directly.
+struct PrepPass {
+  long long sst[4], dst[4], tst[4];
+  int n[4];
+  int ta, tb, o0, o1;
+};
+
+// the pass geometry: source strides sst, destination strides dst (index
+// order l, u, r, d), dims (dx, dy, dx, dy); returns the grid
+static dim3 prep_pass(PrepPass& P, const long long* sst, const long long* dst, int dx, int dy) {
+  const long long nat[4] = {(long long)dy * dx * dy, (long long)dx * dy, dy, 1};
+  for (int i = 0; i < 4; ++i) {
+    P.sst[i] = sst[i];
+    P.dst[i] = dst[i];
+    P.tst[i] = nat[i];
+  }
+  P.n[0] = dx;
+  P.n[1] = dy;
+  P.n[2] = dx;
+  P.n[3] = dy;
+  int ta = 0, tb = -1;
+  for (int i = 0; i < 4; ++i)
+    if (sst[i] == 1) ta = i;
+  for (int i = 0; i < 4; ++i)
+    if (dst[i] == 1 && i != ta) tb = i;
+  if (tb < 0) tb = ta == 3 ? 2 : 3;  // the same unit-stride dim: any other one
+  int rest[2], nr = 0;
+  for (int i = 0; i < 4; ++i)
+    if (i != ta && i != tb) rest[nr++] = i;
+  P.ta = ta;
+  P.tb = tb;
+  P.o0 = rest[0];
+  P.o1 = rest[1];
+  return dim3((unsigned)(((P.n[ta] + 31) / 32) * ((P.n[tb] + 31) / 32)), (unsigned)P.n[rest[0]],
+              (unsigned)P.n[rest[1]]);
+}
+
+// FP64 (or FP32, out_f32) operands of the FP64 path
+__global__ __launch_bounds__(256) void k_prep_pass(const void* src, bool src_f32, PrepPass P,
+                                                   const unsigned long long* maxbits, void* out,
+                                                   bool out_f32) {
+  __shared__ double tile[32][33];
   const double inv = 1.0 / __longlong_as_double((long long)*maxbits);
-  const long long total = (long long)dx * dy * dx * dy;
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
-       e += (long long)gridDim.x * blockDim.x) {
-    long long q = e;
-    int d = (int)(q % dy); q /= dy;
-    int r = (int)(q % dx); q /= dx;
-    int u = (int)(q % dy); q /= dy;
-    int l = (int)q;
-    long long si = rotate ? (((long long)u * dx + l) * dy + d) * dx + r : e;
-    double v = ld_any(src, si, src_f32) * inv;
-    st_any(Tn, e, v, out_f32);
-    // Xt[(l,d),(u,r)]
-    st_any(Xt, (((long long)l * dy + d) * dy + u) * dx + r, v, out_f32);
-    // Tp[(l,u),(d,r)]: T[a,c,e,l] read as rows (a,c), columns (l,e)
-    st_any(Tp, (((long long)l * dy + u) * dy + d) * dx + r, v, out_f32);
+  const int na = P.n[P.ta], nb = P.n[P.tb];
+  const int tiles_a = (na + 31) / 32;
+  const int a0 = (blockIdx.x % tiles_a) * 32, b0 = (blockIdx.x / tiles_a) * 32;
+  const long long sb = blockIdx.y * P.sst[P.o0] + blockIdx.z * P.sst[P.o1];
+  const long long db = blockIdx.y * P.dst[P.o0] + blockIdx.z * P.dst[P.o1];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const bool direct = P.dst[P.ta] == 1;
+  for (int k = ty; k < 32; k += 8) {
+    const int a = a0 + tx, b = b0 + k;
+    double v = 0.0;
+    if (a < na && b < nb) {
+      v = ld_any(src, sb + a * P.sst[P.ta] + b * P.sst[P.tb], src_f32) * inv;
+      if (direct) st_any(out, db + a * P.dst[P.ta] + b * P.dst[P.tb], v, out_f32);
+    }
+    tile[k][tx] = v;
+  }
+  if (direct) return;  // uniform
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) {
+    const int b = b0 + tx, a = a0 + k;
+    if (a < na && b < nb) st_any(out, db + a * P.dst[P.ta] + b * P.dst[P.tb], tile[tx][k], out_f32);
   }
 }
 
 void launch_prep(const void* src, bool src_f32, bool rotate, int dx, int dy,
                  const unsigned long long* maxbits, void* Tn, void* Xt, void* Tp, bool out_f32,
                  hipStream_t s) {
-  long long total = (long long)dx * dy * dx * dy;
-  hipLaunchKernelGGL(k_prep, dim3(nblocks(total, 256)), dim3(256), 0, s, src, src_f32, rotate, dx,
-                     dy, maxbits, Tn, Xt, Tp, out_f32);
+  // index order (l, u, r, d); the source is T~ itself or, rotated, T~[u, l, d, r]
+  const long long X = dx, Y = dy;
+  const long long src_rot[4] = {Y * X, X * Y * X, 1, X};
+  const long long src_nat[4] = {Y * X * Y, X * Y, Y, 1};
+  // Tn natural; Xt[(l,d),(u,r)]; Tp[(l,u),(d,r)]: T[a,c,e,l] read as rows (a,c), columns (l,e)
+  const long long dsts[3][4] = {{Y * X * Y, X * Y, Y, 1},
+                                {Y * Y * X, X, 1, Y * X},
+                                {Y * Y * X, Y * X, 1, X}};
+  void* outs[3] = {Tn, Xt, Tp};
+  for (int o = 0; o < 3; ++o) {
+    PrepPass P{};
+    const dim3 grid = prep_pass(P, rotate ? src_rot : src_nat, dsts[o], dx, dy);
+    hipLaunchKernelGGL(k_prep_pass, grid, dim3(256), 0, s, src, src_f32, P, maxbits, outs[o],
+                       out_f32);
+  }
 }
 
 // The reflected tensor T'[l,u,r,d] = T[r,u,l,d] (FP64, dims (dx,dy,dx,dy)) in
@@ -307,20 +371,7 @@ __device__ __forceinline__ void st_rp(void* hi, void* lo, long long i, float v, 
   }
 }
 
-// One pass of the operand preparation: element (l, u, r, d) of the tensor
-// (dims n = (dx, dy, dx, dy)) is read at sum idx * sst, scaled by 1 / max|T~|,
-// rounded and written at sum idx * dst (and at sum idx * tst into the FP32
-// copy Tn when Tn is given).  The dims ta (unit source stride) and tb (unit
-// destination stride, or another one when that is ta) are tiled 32 x 32;
-// blockIdx.y / z run over the other two.  With different unit-stride dims the
-// tile passes through LDS, so reads run along ta and writes along tb, both
-// coalesced; otherwise both run along ta directly.
-struct PrepPass {
-  long long sst[4], dst[4], tst[4];
-  int n[4];
-  int ta, tb, o0, o1;
-};
-
+// The reduced-precision operands, one PrepPass each (rounded by st_rp).
 __global__ __launch_bounds__(256) void k_prep_rp_pass(const void* src, bool src_f32, PrepPass P,
                                                       const unsigned long long* maxbits,
                                                       void* hi, void* lo, int mode, float* Tn) {
@@ -367,7 +418,6 @@ void launch_prep_rp(const void* src, bool src_f32, bool rotate, int dx, int dy,
   const long long src_rot[4] = {Y * X, X * Y * X, 1, X};
   const long long src_nat[4] = {Y * X * Y, X * Y, Y, 1};
   const long long* sst = rotate ? src_rot : src_nat;
-  const long long nat[4] = {Y * X * Y, X * Y, Y, 1};
   // OT rows (l,u), K (r,d); OX rows (l,d), K (u,r); OC1 rows (u,r,d), K l;
   // OC2 rows (d,r), K (l,u)
   const long long dsts[4][4] = {{Y * ldP, ldP, Y, 1},
@@ -376,30 +426,7 @@ void launch_prep_rp(const void* src, bool src_f32, bool rotate, int dx, int dy,
                                 {Y, 1, ldP, X * ldP}};
   for (int o = 0; o < 4; ++o) {
     PrepPass P{};
-    for (int i = 0; i < 4; ++i) {
-      P.sst[i] = sst[i];
-      P.dst[i] = dsts[o][i];
-      P.tst[i] = nat[i];
-    }
-    P.n[0] = dx;
-    P.n[1] = dy;
-    P.n[2] = dx;
-    P.n[3] = dy;
-    int ta = 0, tb = -1;
-    for (int i = 0; i < 4; ++i)
-      if (sst[i] == 1) ta = i;
-    for (int i = 0; i < 4; ++i)
-      if (dsts[o][i] == 1 && i != ta) tb = i;
-    if (tb < 0) tb = ta == 3 ? 2 : 3;  // same unit-stride dim: any other one
-    int rest[2], nr = 0;
-    for (int i = 0; i < 4; ++i)
-      if (i != ta && i != tb) rest[nr++] = i;
-    P.ta = ta;
-    P.tb = tb;
-    P.o0 = rest[0];
-    P.o1 = rest[1];
-    const dim3 grid((unsigned)(((P.n[ta] + 31) / 32) * ((P.n[tb] + 31) / 32)),
-                    (unsigned)P.n[rest[0]], (unsigned)P.n[rest[1]]);
+    const dim3 grid = prep_pass(P, sst, dsts[o], dx, dy);
     // the FP32 copy goes with OT, whose order it shares
     hipLaunchKernelGGL(k_prep_rp_pass, grid, dim3(256), 0, s, src, src_f32, P, maxbits,
                        ops.hi[o], ops.lo[o], mode, o == 0 ? Tn : nullptr);
