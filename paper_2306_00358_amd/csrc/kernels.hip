@@ -192,22 +192,33 @@ void launch_store(double* p, double v, hipStream_t s) {
 }
 
 // ------------------------------------------------------------ environment --
-__global__ void k_symmetrize(double* M, int n) {
-  long long total = (long long)n * n;
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
-       e += (long long)gridDim.x * blockDim.x) {
-    int r = (int)(e / n), c = (int)(e % n);
-    if (r < c) {
-      double a = M[(long long)r * n + c], b = M[(long long)c * n + r];
-      double v = 0.5 * (a + b);
-      M[(long long)r * n + c] = v;
-      M[(long long)c * n + r] = v;
-    }
+// M <- (M + M^T) / 2 by 32 x 32 tile pairs (I, J), I <= J: both tiles are
+// read coalesced into LDS and written back, each entry 0.5 (M_rc + M_cr)
+// with r < c the upper one; a diagonal tile is its own partner.
+__global__ __launch_bounds__(256) void k_symmetrize(double* M, int n) {
+  const int I = blockIdx.y, J = blockIdx.x;
+  if (I > J) return;  // uniform
+  __shared__ double A[32][33], B[32][33];  // tiles (I, J) and (J, I)
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int r0 = I * 32, c0 = J * 32;
+  for (int k = ty; k < 32; k += 8) {
+    const int r = r0 + k, c = c0 + tx;
+    A[k][tx] = (r < n && c < n) ? M[(long long)r * n + c] : 0.0;
+    const int r2 = c0 + k, c2 = r0 + tx;
+    B[k][tx] = (r2 < n && c2 < n) ? M[(long long)r2 * n + c2] : 0.0;
+  }
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) {
+    const int r = r0 + k, c = c0 + tx;  // in tile (I, J): M_rc = A[k][tx], M_cr = B[tx][k]
+    if (r < n && c < n && r < c) M[(long long)r * n + c] = 0.5 * (A[k][tx] + B[tx][k]);
+    const int r2 = c0 + k, c2 = r0 + tx;  // in tile (J, I), lower: upper partner (c2, r2)
+    if (r2 < n && c2 < n && c2 < r2) M[(long long)r2 * n + c2] = 0.5 * (A[tx][k] + B[k][tx]);
   }
 }
 
 void launch_symmetrize(double* M, int n, hipStream_t s) {
-  hipLaunchKernelGGL(k_symmetrize, dim3(nblocks((long long)n * n, 256)), dim3(256), 0, s, M, n);
+  const int T = (n + 31) / 32;
+  hipLaunchKernelGGL(k_symmetrize, dim3(T, T), dim3(256), 0, s, M, n);
 }
 
 // --------------------------------------------------------------- spectrum --
