@@ -28,8 +28,9 @@
 //             (and once no such check misses, only the first sweep after a
 //             check is checked).
 // Check:      H = V (V M)^T, H = Z diag(theta) Z^T (Householder reduction to
-//             tridiagonal form in one workgroup, then rocSOLVER's divide and
-//             conquer on the tridiagonal, which applies the reduction),
+//             tridiagonal form in one workgroup, k_sytrd_small, then divide
+//             and conquer on the tridiagonal in another, k_stedc_small in
+//             stedc.hip, and one small GEMM for Z^T = Z_T^T Q^T),
 //             Ritz vectors X = Z^T V, residuals |(Z^T Y)_i - theta_i X_i|.
 // Converged when the residuals of the `need` leading pairs are below
 // tol * theta_1; otherwise the sweeps continue from X.  The first check
@@ -42,8 +43,6 @@
 // All products are FP64 MFMA GEMMs; the host reads p Ritz values and
 // residuals per check.
 #include <hip/hip_runtime.h>
-#include <rocblas/rocblas.h>
-#include <rocsolver/rocsolver.h>
 
 #include <cmath>
 #include <vector>
@@ -894,7 +893,7 @@ size_t topk_workspace_doubles(int n, int p) {
 // the next group is checked; *nocheck carries that state to the next solve.
 // Every Rayleigh-Ritz step still sees a basis from three passes, and its
 // residuals decide convergence.
-bool topk_eigs(rocblas_handle blas, const double* M, int n, int p, int need, double tol,
+bool topk_eigs(const double* M, int n, int p, int need, double tol,
                int q_first, double* shift, int* nocheck, double* ws, double* W, double* Xout,
                int* dinfo, int* iters, int* enough, double* resid, hipStream_t s) {
   const size_t pn = (size_t)p * n, pp = (size_t)p * p;

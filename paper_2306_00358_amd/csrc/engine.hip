@@ -568,7 +568,7 @@ static const double* leading_eigs(hotrg_ctx* c, Buf& Mb, Buf& Wb, Buf& Xb, int n
       h.shift = 0.0;
       h.nocheck = 0;
     }
-    const bool ok = topk_eigs(c->blas, (const double*)Mb.p, n, p, need, tol, q_first, &h.shift,
+    const bool ok = topk_eigs((const double*)Mb.p, n, p, need, tol, q_first, &h.shift,
                               &h.nocheck, (double*)c->EW.p, (double*)Wb.p, (double*)Xb.p,
                               (int*)((char*)c->scal.p + 48), &iters, &enough, &resid, c->stream);
     h.n = ok ? n : 0;

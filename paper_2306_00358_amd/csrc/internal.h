@@ -222,7 +222,7 @@ struct CholItem {
 };
 void launch_chol_inv_batched(const CholItem* d_items, int count, int pmax, int pass, bool full,
                              hipStream_t s);
-bool topk_eigs(rocblas_handle blas, const double* M, int n, int p, int need, double tol,
+bool topk_eigs(const double* M, int n, int p, int need, double tol,
                int q_first, double* shift, int* nocheck, double* ws, double* W, double* Xout,
                int* dinfo, int* iters, int* enough, double* resid, hipStream_t s);
 void launch_layout_u(const double* Ucan, int dx, int dn, void* U1, void* U3, bool out_f32,
