@@ -676,9 +676,8 @@ __device__ __forceinline__ double trd_sum8(double v) {
   return v + trd_dpp<0x141>(v);
 }
 
-__global__ __launch_bounds__(kTrdThreads) void k_sytrd_small(double* __restrict__ H, int p,
-                                                             double* __restrict__ d,
-                                                             double* __restrict__ e) {
+__device__ __forceinline__ void sytrd_body(double* __restrict__ H, int p, double* __restrict__ d,
+                                           double* __restrict__ e) {
   // reflector k at Vr[128 k + c], zero outside its columns k+1 .. p-1; the
   // vectors of a step are likewise zero outside the trailing block, so the
   // register loops below need no bounds tests
@@ -799,6 +798,31 @@ __global__ __launch_bounds__(kTrdThreads) void k_sytrd_small(double* __restrict_
       if (c < p) H[c + i * p] = a[r];
     }
   }
+}
+
+__global__ __launch_bounds__(kTrdThreads) void k_sytrd_small(double* __restrict__ H, int p,
+                                                             double* __restrict__ d,
+                                                             double* __restrict__ e) {
+  sytrd_body(H, p, d, e);
+}
+
+// The same reduction for every problem of a lockstep batch whose block
+// eigensolver is still iterating: H (p x p) -> Q^T, diagonal into W, the
+// off-diagonal into G (free during the Rayleigh-Ritz step).
+__global__ __launch_bounds__(kTrdThreads) void k_group_sytrd(const GroupStep* __restrict__ dsc) {
+  const GroupStep& g = dsc[blockIdx.x];
+  if (!g.ctl->iter) return;  // uniform
+  sytrd_body(g.H, g.p, g.W, g.G);
+}
+
+void group_sytrd(const GroupStep* d, int count, int pmax, hipStream_t s) {
+  static bool lds_set = hipFuncSetAttribute((const void*)k_group_sytrd,
+                                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                                            (int)((size_t)128 * 128 * sizeof(double))) ==
+                        hipSuccess;
+  (void)lds_set;
+  hipLaunchKernelGGL(k_group_sytrd, dim3(count), dim3(kTrdThreads),
+                     (size_t)128 * pmax * sizeof(double), s, d);
 }
 
 __global__ void k_symmetrize_small(double* H, int p) {

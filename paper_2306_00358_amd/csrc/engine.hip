@@ -937,8 +937,9 @@ void group_sweep(hotrg_ctx* c, GRun& R, bool tune, std::vector<std::vector<long 
     launch_symmetrize((double*)g->M.p, g->n, s);
     launch_trace((const double*)g->M.p, g->n, (double*)((char*)g->scal.p + 8), s);
   }
-  // leading eigenpairs: block subspace iteration with a fixed budget, or the
-  // whole (small) environment by Jacobi
+  // leading eigenpairs: block subspace iteration with a fixed budget (its
+  // Rayleigh-Ritz matrices by tridiagonal divide and conquer), or the whole
+  // (small) environment by Jacobi
   group_begin(R.steps, G, s);
   if (R.dense) group_dense(R.steps, G, R.pmax, s);
   if (!R.dense) group_seed(R.steps, G, R.max_pn, s);
@@ -963,7 +964,8 @@ void group_sweep(hotrg_ctx* c, GRun& R, bool tune, std::vector<std::vector<long 
     launch_f64_table(R.vm, B_NCONTIG, s);    // Y = V M
     launch_f64_table(R.rrH, B_KCONTIG, s);   // H = V Y^T
     group_symm_h(R.steps, G, s);
-    group_jacobi(R.steps, G, R.pmax, s);     // H <- Z^T, W ascending
+    group_sytrd(R.steps, G, R.pmax, s);      // H -> Q^T, tridiagonal into W, G
+    group_stedc(R.steps, G, R.pmax, s);      // H <- Z^T, W ascending
     launch_f64_table(R.rrX, B_NCONTIG, s);   // X = Z^T V
     launch_f64_table(R.rrYx, B_NCONTIG, s);  // Yx = Z^T Y
     group_resid(R.steps, G, round == kGroupRounds - 1, s);

@@ -14,8 +14,11 @@
 // Block eigensolver of a batch: the subspace iteration of eigs.hip with a
 // fixed budget (rounds of sweeps, each round ending in a Rayleigh-Ritz check
 // on the device), so that no host read decides the number of sweeps; the
-// p x p Rayleigh-Ritz matrices are diagonalised by a parallel two-sided
-// Jacobi method (one workgroup per problem): in each of the p - 1 rounds of a
+// p x p Rayleigh-Ritz matrices go through the Householder reduction and the
+// tridiagonal divide and conquer of the per-problem path (one workgroup per
+// problem, eigs.hip and stedc.hip).  Small environments are diagonalised
+// whole by a parallel two-sided Jacobi method (one workgroup per problem,
+// below): in each of the p - 1 rounds of a
 // sweep the p indices form p/2 disjoint pairs (a round-robin tournament, so
 // every pair meets once per sweep); each pair's 2 x 2 rotation annihilates
 // its off-diagonal element, and the rotations of one round, acting on

@@ -103,11 +103,13 @@ __device__ __forceinline__ DcMerge dc_merge_of(int s, int D, int n) {
   return m;
 }
 
-// din may be W: it is read before the first barrier and W written after the last
-__global__ __launch_bounds__(kDcThreads) void k_stedc_small(const double* din, const double* ein,
-                                                            int n, double* W,
-                                                            double* __restrict__ Zt,
-                                                            int* __restrict__ info) {
+// din may be W: it is read before the first barrier and W written after the
+// last.  With Hb (n x n, row-major, holding Q^T of a Householder reduction
+// Q^T A Q = T) the eigenvectors leave as the rows of Z^T Q^T over Hb instead
+// of Z^T into Zt: row c of Hb becomes A's eigenvector for W[c].
+__device__ __forceinline__ void stedc_body(const double* din, const double* ein, int n, double* W,
+                                           double* __restrict__ Zt, double* __restrict__ Hb,
+                                           int* __restrict__ info) {
   extern __shared__ double Z[];  // n rows of kDcLd: Z[r * kDcLd + c]
   __shared__ double lam[kDcMax], e[kDcMax], zv[kDcMax];
   __shared__ double sd[kDcMax], sz[kDcMax];
@@ -505,11 +507,76 @@ __global__ __launch_bounds__(kDcThreads) void k_stedc_small(const double* din, c
     if (!(fabs(lv) < INFINITY)) bad = 1;
   }
   __syncthreads();
-  for (int x = t; x < n * n; x += kDcThreads) {
-    const int c = x / n, r = x % n;
-    Zt[x] = Z[r * kDcLd + ord[c]];
+  if (Hb) {
+    // (Q z_c)_i = sum_k Hb[k][i] Z[k][ord[c]]: thread (i, group cg) forms
+    // columns i of rows c = cg, cg + 8, ..; every read of Hb precedes the
+    // barrier, every write follows it
+    const int i = t & 127, cg = t >> 7;
+    double acc[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+    if (i < n) {
+#pragma unroll
+      for (int half = 0; half < 16; half += 8) {  // eight rows at a time: fewer live indices
+        int col[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int c = cg + 8 * (half + q);
+          col[q] = ord[c < n ? c : 0];
+        }
+        for (int k = 0; k < n; ++k) {
+          const double h = Hb[(long long)k * n + i];
+          const double* zr = Z + k * kDcLd;
+#pragma unroll
+          for (int q = 0; q < 8; ++q) acc[half + q] += h * zr[col[q]];
+        }
+      }
+    }
+    __syncthreads();
+    if (i < n) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int c = cg + 8 * q;
+        if (c < n) Hb[(long long)c * n + i] = acc[q];
+      }
+    }
+  } else {
+    for (int x = t; x < n * n; x += kDcThreads) {
+      const int c = x / n, r = x % n;
+      Zt[x] = Z[r * kDcLd + ord[c]];
+    }
   }
   if (t == 0) *info = bad;
+}
+
+__global__ __launch_bounds__(kDcThreads) void k_stedc_small(const double* din, const double* ein,
+                                                            int n, double* W,
+                                                            double* __restrict__ Zt,
+                                                            int* __restrict__ info) {
+  stedc_body(din, ein, n, W, Zt, nullptr, info);
+}
+
+// Every problem of a lockstep batch whose block eigensolver is still
+// iterating: the tridiagonal (diagonal in W, off-diagonal in G) of its
+// Rayleigh-Ritz matrix, whose reduction matrix Q^T is in H, becomes W
+// ascending and H = the Ritz coefficient rows; a non-finite result marks
+// the problem failed (it is then run again alone).
+__global__ __launch_bounds__(kDcThreads) void k_group_stedc(const GroupStep* __restrict__ dsc) {
+  const GroupStep& g = dsc[blockIdx.x];
+  if (!g.ctl->iter) return;  // uniform
+  __shared__ int bad_out;
+  stedc_body(g.W, g.G, g.p, g.W, nullptr, g.H, &bad_out);
+  if (threadIdx.x == 0 && bad_out) g.ctl->fail = 1;  // thread 0 wrote bad_out itself
+}
+
+void group_stedc(const GroupStep* d, int count, int pmax, hipStream_t s) {
+  static bool lds_set = hipFuncSetAttribute((const void*)k_group_stedc,
+                                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                                            (int)((size_t)kDcMax * kDcLd * sizeof(double))) ==
+                        hipSuccess;
+  (void)lds_set;
+  hipLaunchKernelGGL(k_group_stedc, dim3(count), dim3(kDcThreads),
+                     (size_t)pmax * kDcLd * sizeof(double), s, d);
 }
 
 bool tridiag_eig_small(const double* d, const double* e, int n, double* W, double* Zt, int* info,
