@@ -128,3 +128,19 @@ def test_run_dcut64_reduced_vs_fp64_oracle(ctx, prec):
     say(prec, "D=64 K=30 lnZ/N %.15f oracle %.15f rel %.3e onsager rel %.3e" % (
         got["lnz_per_site"], ref, rel, abs(got["lnz_per_site"] - exact.onsager_tc()) / exact.onsager_tc()))
     assert rel <= 1e-7
+
+
+@pytest.mark.parametrize("prec, u", [("fp64", 0.0), ("fp32", 2.0 ** -24), ("bf16x3", 2.0 ** -17)])
+def test_eigensolver_residual_matches_the_step_precision(ctx, prec, u):
+    # the last step of a D_cut = 32 run at T_c (n = 1024: the block solver)
+    # stops at a relative Ritz residual of 5e-14 when it is FP64 and of
+    # 2^-10 u_p when its contractions ran in precision p, whose environment
+    # already carries rounding of relative size u_p
+    beta = math.log(1.0 + math.sqrt(2.0)) / 2.0
+    got = _run(ctx, 32, 30, prec, beta)
+    sweeps, resid = ctx.last_eig()
+    tol = max(5e-14, u * 2.0 ** -10)
+    say(prec, "last solve: sweeps", sweeps, "residual %.3e" % resid, "target %.3e" % tol,
+        "lnZ/N %.15f" % got["lnz_per_site"])
+    assert sweeps > 0
+    assert resid <= tol
