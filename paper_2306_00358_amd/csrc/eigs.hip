@@ -806,6 +806,22 @@ __global__ __launch_bounds__(kTrdThreads) void k_sytrd_small(double* __restrict_
   sytrd_body(H, p, d, e);
 }
 
+// All eigenpairs of a small symmetric matrix M (n x n, 3 <= n <= 128,
+// row-major, overwritten): W ascending, M <- the eigenvector rows (row c for
+// W[c]); E (n doubles) is scratch, *info = 1 when a result is not finite.
+// Two single-workgroup launches: the Householder reduction and the divide and
+// conquer with its back-transform.
+bool dense_eig_small(double* M, int n, double* W, double* E, int* info, hipStream_t s) {
+  static bool lds_set = hipFuncSetAttribute((const void*)k_sytrd_small,
+                                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                                            (int)((size_t)128 * 128 * sizeof(double))) ==
+                        hipSuccess;
+  if (!lds_set || n < 3 || n > 128) return false;
+  hipLaunchKernelGGL(k_sytrd_small, dim3(1), dim3(kTrdThreads), (size_t)128 * n * sizeof(double),
+                     s, M, n, W, E);
+  return tridiag_eig_small_back(W, E, n, W, M, info, s);
+}
+
 // The same reduction for every problem of a lockstep batch whose block
 // eigensolver is still iterating: H (p x p) -> Q^T, diagonal into W, the
 // off-diagonal into G (free during the Rayleigh-Ritz step).

@@ -582,10 +582,14 @@ static const double* leading_eigs(hotrg_ctx* c, Buf& Mb, Buf& Wb, Buf& Xb, int n
   }
   ensure(c, c->E, (size_t)n * 8);
   c->last_eig_iters = 0;  // dense
-  rocblas_status rs = rocsolver_dsyevd(c->blas, rocblas_evect_original, rocblas_fill_lower, n,
-                                       (double*)Mb.p, n, (double*)Wb.p, (double*)c->E.p, inf);
-  if (rs != rocblas_status_success)
-    fail(HOTRG_ERR_DEVICE, "rocsolver_dsyevd failed with status " + std::to_string((int)rs));
+  // small environments: two single-workgroup launches (Householder reduction,
+  // divide and conquer with the back-transform); larger ones rocSOLVER dsyevd
+  if (!dense_eig_small((double*)Mb.p, n, (double*)Wb.p, (double*)c->E.p, inf, c->stream)) {
+    rocblas_status rs = rocsolver_dsyevd(c->blas, rocblas_evect_original, rocblas_fill_lower, n,
+                                         (double*)Mb.p, n, (double*)Wb.p, (double*)c->E.p, inf);
+    if (rs != rocblas_status_success)
+      fail(HOTRG_ERR_DEVICE, "rocsolver_dsyevd failed with status " + std::to_string((int)rs));
+  }
   // a non-converged solve marks the caller's flag: later solves overwrite `inf`
   launch_fold_info(inf, sticky, 0, c->stream);
   *cols_out = n;

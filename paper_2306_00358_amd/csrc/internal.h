@@ -182,6 +182,14 @@ void launch_layout_u_rp(const double* Ucan, int dx, int dn, int mode, void* u1hi
 // finite.  False when the launch fails.
 bool tridiag_eig_small(const double* d, const double* e, int n, double* W, double* Zt, int* info,
                        hipStream_t s);
+// The same with the back-transform: Hb (n x n) holds Q^T of the Householder
+// reduction on entry and the eigenvector rows (row c for W[c]) on exit.
+bool tridiag_eig_small_back(const double* d, const double* e, int n, double* W, double* Hb,
+                            int* info, hipStream_t s);
+// All eigenpairs of a small symmetric matrix (3 <= n <= 128, row-major, over
+// M): W ascending, M <- eigenvector rows; E (n) scratch; false when not
+// applicable or the launch fails.
+bool dense_eig_small(double* M, int n, double* W, double* E, int* info, hipStream_t s);
 
 // ---- small kernels (kernels.hip) ----
 void launch_maxabs(const void* x, long long n, bool is_f32, unsigned long long* maxbits, hipStream_t s);

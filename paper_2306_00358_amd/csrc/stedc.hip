@@ -579,6 +579,28 @@ void group_stedc(const GroupStep* d, int count, int pmax, hipStream_t s) {
                      (size_t)pmax * kDcLd * sizeof(double), s, d);
 }
 
+// The same with the back-transform: Hb (n x n) holds Q^T on entry and the
+// eigenvector rows on exit.
+__global__ __launch_bounds__(kDcThreads) void k_stedc_small_back(const double* din,
+                                                                 const double* ein, int n,
+                                                                 double* W,
+                                                                 double* __restrict__ Hb,
+                                                                 int* __restrict__ info) {
+  stedc_body(din, ein, n, W, nullptr, Hb, info);
+}
+
+bool tridiag_eig_small_back(const double* d, const double* e, int n, double* W, double* Hb,
+                            int* info, hipStream_t s) {
+  static bool lds_set = hipFuncSetAttribute((const void*)k_stedc_small_back,
+                                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                                            (int)((size_t)kDcMax * kDcLd * sizeof(double))) ==
+                        hipSuccess;
+  if (!lds_set || n < 1 || n > kDcMax) return false;
+  hipLaunchKernelGGL(k_stedc_small_back, dim3(1), dim3(kDcThreads),
+                     (size_t)n * kDcLd * sizeof(double), s, d, e, n, W, Hb, info);
+  return hipGetLastError() == hipSuccess;
+}
+
 bool tridiag_eig_small(const double* d, const double* e, int n, double* W, double* Zt, int* info,
                        hipStream_t s) {
   static bool lds_set = hipFuncSetAttribute((const void*)k_stedc_small,
