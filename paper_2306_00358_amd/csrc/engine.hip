@@ -943,7 +943,7 @@ void group_sweep(hotrg_ctx* c, GRun& R, bool tune, std::vector<std::vector<long 
   }
   // leading eigenpairs: block subspace iteration with a fixed budget (its
   // Rayleigh-Ritz matrices by tridiagonal divide and conquer), or the whole
-  // (small) environment by Jacobi
+  // (small) environment by the same divide and conquer
   group_begin(R.steps, G, s);
   if (R.dense) group_dense(R.steps, G, R.pmax, s);
   if (!R.dense) group_seed(R.steps, G, R.max_pn, s);
@@ -1319,9 +1319,9 @@ void run_grouped_impl(hotrg_ctx* c, int N, const hotrg_model_params* params,
         g.need = std::max(g.D + 1, std::min(g.o.spec_len, g.n));
         g.p = (std::min(128, std::max(2 * g.D, g.need + 16)) + 15) / 16 * 16;
         const bool block = g.need + 16 <= g.p && g.p <= 128 && 4 * g.p <= g.n;
-        // small environments: Jacobi on the whole matrix, padded to even size
+        // small environments: the whole matrix, padded to even size (at least 4)
         g.dense = !block && g.n <= 96;
-        if (g.dense) g.p = g.n + (g.n & 1);
+        if (g.dense) g.p = std::max(4, g.n + (g.n & 1));
         ok = block || g.dense;
       }
       if (ok && group_sp < 0) {

@@ -16,15 +16,9 @@
 // on the device), so that no host read decides the number of sweeps; the
 // p x p Rayleigh-Ritz matrices go through the Householder reduction and the
 // tridiagonal divide and conquer of the per-problem path (one workgroup per
-// problem, eigs.hip and stedc.hip).  Small environments are diagonalised
-// whole by a parallel two-sided Jacobi method (one workgroup per problem,
-// below): in each of the p - 1 rounds of a
-// sweep the p indices form p/2 disjoint pairs (a round-robin tournament, so
-// every pair meets once per sweep); each pair's 2 x 2 rotation annihilates
-// its off-diagonal element, and the rotations of one round, acting on
-// disjoint index pairs, are applied to the matrix (in LDS) as independent
-// 2 x 2 blocks R_a^T H_ab R_b, and to the accumulated eigenvectors.  Sweeps
-// stop when no off-diagonal element exceeds 2^-53 sqrt(|h_ii h_jj|).
+// problem, eigs.hip and stedc.hip); small environments (n <= 96) go through
+// the same two kernels whole, copied into H with a zero row and column when
+// n is odd (one extra eigenvalue 0 below the spectrum).
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -65,108 +59,6 @@ __global__ void k_group_symm_h(const GroupStep* __restrict__ d) {
       s.H[i * p + j] = v;
       s.H[j * p + i] = v;
     }
-  }
-}
-
-constexpr int kJacThreads = 256;
-constexpr int kJacMaxSweeps = 40;
-
-// index at tournament position q in round r (position 0 stays)
-__device__ __forceinline__ int jac_player(int q, int r, int p) {
-  return q == 0 ? 0 : 1 + (q - 1 + r) % (p - 1);
-}
-
-// H (p x p, symmetric) -> W (p eigenvalues, ascending) and H overwritten by
-// Z^T (row c = eigenvector c, same order).  Z^T is accumulated in LDS next to
-// the matrix when both fit (vt_lds: p <= 96), else in T2 (p x p, global).
-__global__ __launch_bounds__(kJacThreads) void k_group_jacobi(const GroupStep* __restrict__ d,
-                                                              int vt_lds) {
-  const GroupStep& s = d[blockIdx.x];
-  if (!s.ctl->iter) return;
-  extern __shared__ double A[];            // p x p (then Z^T, p x p, with vt_lds)
-  __shared__ double cs_c[64], cs_s[64];    // rotation of pair m
-  __shared__ int pi[64], pj[64];           // its indices, pi < pj
-  __shared__ int rot;
-  __shared__ int rank_s[128];
-  const int p = s.p, h = p / 2, t = threadIdx.x;
-  double* Vt = vt_lds ? A + p * p : s.T2;
-  for (int e = t; e < p * p; e += kJacThreads) {
-    A[e] = s.H[e];
-    Vt[e] = (e / p == e % p) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  const double eps = 1.1102230246251565e-16;  // 2^-53
-  int sweep = 0;
-  for (; sweep < kJacMaxSweeps; ++sweep) {
-    if (t == 0) rot = 0;
-    __syncthreads();
-    for (int r = 0; r < p - 1; ++r) {
-      if (t < h) {
-        int i = jac_player(t, r, p), j = jac_player(p - 1 - t, r, p);
-        if (i > j) { const int x = i; i = j; j = x; }
-        const double aii = A[i * p + i], ajj = A[j * p + j], aij = A[i * p + j];
-        double c = 1.0, sn = 0.0;
-        if (aij != 0.0 && fabs(aij) > eps * sqrt(fabs(aii * ajj))) {
-          const double tau = (ajj - aii) / (2.0 * aij);
-          const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-          c = 1.0 / sqrt(1.0 + tt * tt);
-          sn = tt * c;
-          rot = 1;
-        }
-        cs_c[t] = c;
-        cs_s[t] = sn;
-        pi[t] = i;
-        pj[t] = j;
-      }
-      __syncthreads();
-      // A <- P^T A P as independent 2 x 2 blocks (pair m1 rows, pair m2 columns)
-      for (int b = t; b < h * h; b += kJacThreads) {
-        const int m1 = b / h, m2 = b % h;
-        const int i1 = pi[m1], j1 = pj[m1], i2 = pi[m2], j2 = pj[m2];
-        const double c1 = cs_c[m1], s1 = cs_s[m1], c2 = cs_c[m2], s2 = cs_s[m2];
-        const double x11 = A[i1 * p + i2], x12 = A[i1 * p + j2];
-        const double x21 = A[j1 * p + i2], x22 = A[j1 * p + j2];
-        const double t11 = x11 * c2 - x12 * s2, t12 = x11 * s2 + x12 * c2;
-        const double t21 = x21 * c2 - x22 * s2, t22 = x21 * s2 + x22 * c2;
-        double a12 = c1 * t12 - s1 * t22, a21 = s1 * t11 + c1 * t21;
-        if (m1 == m2) a12 = a21 = 0.0;
-        A[i1 * p + i2] = c1 * t11 - s1 * t21;
-        A[i1 * p + j2] = a12;
-        A[j1 * p + i2] = a21;
-        A[j1 * p + j2] = s1 * t12 + c1 * t22;
-      }
-      // Z <- Z P, i.e. rows i, j of Z^T rotate
-      for (int e = t; e < h * p; e += kJacThreads) {
-        const int m = e / p, col = e % p;
-        const int i = pi[m], j = pj[m];
-        const double c = cs_c[m], sn = cs_s[m];
-        const double vi = Vt[i * p + col], vj = Vt[j * p + col];
-        Vt[i * p + col] = c * vi - sn * vj;
-        Vt[j * p + col] = sn * vi + c * vj;
-      }
-      __syncthreads();
-    }
-    // every thread reads the flag before thread 0 clears it for the next sweep
-    const int any = rot;
-    __syncthreads();
-    if (!any) break;
-  }
-  if (sweep == kJacMaxSweeps && t == 0) s.ctl->fail = 1;
-  // ascending order: rank of each diagonal value (ties by index)
-  if (t < p) {
-    const double w = A[t * p + t];
-    int rk = 0;
-    for (int j = 0; j < p; ++j) {
-      const double x = A[j * p + j];
-      rk += (x < w || (x == w && j < t)) ? 1 : 0;
-    }
-    rank_s[t] = rk;
-    s.W[rk] = w;
-  }
-  __syncthreads();
-  for (int e = t; e < p * p; e += kJacThreads) {
-    const int i = e / p, col = e % p;
-    s.H[rank_s[i] * p + col] = Vt[e];
   }
 }
 
@@ -232,10 +124,10 @@ __global__ void k_group_restart(const GroupStep* __restrict__ d) {
     s.V[e] = s.X[e];
 }
 
-// Small environments (n <= 96) are diagonalised whole by the Jacobi kernel:
-// H = M padded with zero rows and columns to the even size p (a padded index
-// adds an eigenvalue 0 below the spectrum), and the eigenvectors' first n
-// components become the rows of X.
+// Small environments (n <= 96) are diagonalised whole by the Householder
+// reduction and the divide and conquer: H = M padded with zero rows and
+// columns to the size p (a padded index adds an eigenvalue 0 below the
+// spectrum), and the eigenvectors' first n components become the rows of X.
 __global__ void k_group_dense_in(const GroupStep* __restrict__ d) {
   const GroupStep& s = d[blockIdx.y];
   if (!s.ctl->iter) return;
@@ -361,18 +253,6 @@ void group_seed(const GroupStep* d, int count, long long max_pn, hipStream_t s) 
 void group_symm_h(const GroupStep* d, int count, hipStream_t s) {
   hipLaunchKernelGGL(k_group_symm_h, dim3(16, count), dim3(256), 0, s, d);
 }
-void group_jacobi(const GroupStep* d, int count, int pmax, hipStream_t s) {
-  static bool lds_set = [] {
-    return hipFuncSetAttribute((const void*)k_group_jacobi,
-                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                               2 * 96 * 96 * (int)sizeof(double)) == hipSuccess;
-  }();
-  (void)lds_set;
-  // the matrix and its eigenvectors both in LDS up to p = 96 (144 KB)
-  const int vt_lds = pmax <= 96 ? 1 : 0;
-  hipLaunchKernelGGL(k_group_jacobi, dim3(count), dim3(kJacThreads),
-                     (size_t)(vt_lds + 1) * pmax * pmax * sizeof(double), s, d, vt_lds);
-}
 void group_resid(const GroupStep* d, int count, bool last, hipStream_t s) {
   hipLaunchKernelGGL(k_group_resid, dim3(count), dim3(256), 0, s, d, last ? 1 : 0);
 }
@@ -384,7 +264,8 @@ void group_restart(const GroupStep* d, int count, long long max_pn, hipStream_t 
 }
 void group_dense(const GroupStep* d, int count, int pmax, hipStream_t s) {
   hipLaunchKernelGGL(k_group_dense_in, dim3(16, count), dim3(256), 0, s, d);
-  group_jacobi(d, count, pmax, s);
+  group_sytrd(d, count, pmax, s);
+  group_stedc(d, count, pmax, s);
   hipLaunchKernelGGL(k_group_dense_out, dim3(16, count), dim3(256), 0, s, d);
 }
 void group_spectrum(const GroupStep* d, int count, hipStream_t s) {

@@ -273,17 +273,16 @@ struct GroupStep {
 void group_begin(const GroupStep* d, int count, hipStream_t s);
 void group_seed(const GroupStep* d, int count, long long max_pn, hipStream_t s);
 void group_symm_h(const GroupStep* d, int count, hipStream_t s);
-void group_jacobi(const GroupStep* d, int count, int pmax, hipStream_t s);
 // Rayleigh-Ritz matrices H (p x p, p a multiple of 16, <= 128) of the
 // iterating problems: Householder reduction (diagonal into W, off-diagonal
 // into G, Q^T over H), then divide and conquer with the back-transform:
-// W ascending, H <- Z^T (row c = eigenvector c), as group_jacobi leaves them
+// W ascending, H <- Z^T (row c = eigenvector c)
 void group_sytrd(const GroupStep* d, int count, int pmax, hipStream_t s);
 void group_stedc(const GroupStep* d, int count, int pmax, hipStream_t s);
 void group_resid(const GroupStep* d, int count, bool last, hipStream_t s);
 void group_restart(const GroupStep* d, int count, long long max_pn, hipStream_t s);
 void group_shift(const GroupStep* d, int count, long long max_pn, hipStream_t s);
-// whole small environments (n <= 96, p = n rounded up to even) by Jacobi
+// whole small environments (n <= 96, p = n rounded up to even) by the same two kernels
 void group_dense(const GroupStep* d, int count, int pmax, hipStream_t s);
 void group_spectrum(const GroupStep* d, int count, hipStream_t s);
 void group_norm(const GroupStep* d, int count, hipStream_t s);

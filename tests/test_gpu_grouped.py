@@ -1,5 +1,6 @@
 """Lockstep batches (hotrg_run_grouped): grouped launches over uneven problems,
-the batched block eigensolver with Jacobi Rayleigh-Ritz, one HIP graph per
+the batched block eigensolver (Rayleigh-Ritz by tridiagonal divide and
+conquer), one HIP graph per
 sweep.  FP64 results against the oracle (ln Z/N at 1e-12, per-step spectra
 at the conditioning tolerance of tests/sensitivity.py); every result against
 the same problem run alone; replays of the captured sweep actually used."""
@@ -115,9 +116,10 @@ def test_grouped_repeatable_and_in_any_order(torch_cuda):
     assert c[0]["lnz_per_site"] == a[0]["lnz_per_site"]
 
 
-def test_grouped_small_environments_dense_jacobi(torch_cuda):
-    # environments of at most 96 rows are diagonalised whole by the Jacobi
-    # kernel (odd sizes padded to even): D_cut = 8 (n = 64) and 9 (n = 81)
+def test_grouped_small_environments_dense(torch_cuda):
+    # environments of at most 96 rows are diagonalised whole (Householder
+    # reduction, divide and conquer; odd sizes padded to even): D_cut = 8
+    # (n = 64) and 9 (n = 81)
     from paper_2306_00358_amd import Context, hotrg_run, hotrg_run_grouped, make_opts, model_params
 
     cases = [("ising", BETA_C, 0, 8, 20), ("ising", 0.42, 0, 9, 16), ("xy", 1.1, 1, 8, 14),
