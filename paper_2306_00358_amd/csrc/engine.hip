@@ -840,7 +840,7 @@ struct GProb {
   hotrg_state* st = nullptr;
   std::vector<int> dxs, dys, dns;
   int D = 0, n = 0, p = 0, need = 0, sp = HOTRG_FP64;  // steady dims, block size, precision
-  bool dense = false;  // environment diagonalised whole (n <= 96) instead of a block
+  bool dense = false;  // environment diagonalised whole (n <= 128) instead of a block
   Buf M, eig, U, scal, Tt, U1, U3;
   Buf RA1[2], RA2[2], RX1[2], RX2[2], RU1[2], RU3[2];
   GroupCtl* ctl = nullptr;  // device
@@ -1320,7 +1320,7 @@ void run_grouped_impl(hotrg_ctx* c, int N, const hotrg_model_params* params,
         g.p = (std::min(128, std::max(2 * g.D, g.need + 16)) + 15) / 16 * 16;
         const bool block = g.need + 16 <= g.p && g.p <= 128 && 4 * g.p <= g.n;
         // small environments: the whole matrix, padded to even size (at least 4)
-        g.dense = !block && g.n <= 96;
+        g.dense = !block && g.n <= 128;
         if (g.dense) g.p = std::max(4, g.n + (g.n & 1));
         ok = block || g.dense;
       }

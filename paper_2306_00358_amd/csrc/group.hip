@@ -16,7 +16,7 @@
 // on the device), so that no host read decides the number of sweeps; the
 // p x p Rayleigh-Ritz matrices go through the Householder reduction and the
 // tridiagonal divide and conquer of the per-problem path (one workgroup per
-// problem, eigs.hip and stedc.hip); small environments (n <= 96) go through
+// problem, eigs.hip and stedc.hip); small environments (n <= 128) go through
 // the same two kernels whole, copied into H with a zero row and column when
 // n is odd (one extra eigenvalue 0 below the spectrum).
 #include <hip/hip_runtime.h>
@@ -124,7 +124,7 @@ __global__ void k_group_restart(const GroupStep* __restrict__ d) {
     s.V[e] = s.X[e];
 }
 
-// Small environments (n <= 96) are diagonalised whole by the Householder
+// Small environments (n <= 128) are diagonalised whole by the Householder
 // reduction and the divide and conquer: H = M padded with zero rows and
 // columns to the size p (a padded index adds an eigenvalue 0 below the
 // spectrum), and the eigenvectors' first n components become the rows of X.

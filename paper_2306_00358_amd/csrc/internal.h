@@ -282,7 +282,7 @@ void group_stedc(const GroupStep* d, int count, int pmax, hipStream_t s);
 void group_resid(const GroupStep* d, int count, bool last, hipStream_t s);
 void group_restart(const GroupStep* d, int count, long long max_pn, hipStream_t s);
 void group_shift(const GroupStep* d, int count, long long max_pn, hipStream_t s);
-// whole small environments (n <= 96, p = n rounded up to even) by the same two kernels
+// whole small environments (n <= 128, p = n rounded up to even) by the same two kernels
 void group_dense(const GroupStep* d, int count, int pmax, hipStream_t s);
 void group_spectrum(const GroupStep* d, int count, hipStream_t s);
 void group_norm(const GroupStep* d, int count, hipStream_t s);

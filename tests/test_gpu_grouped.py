@@ -117,13 +117,14 @@ def test_grouped_repeatable_and_in_any_order(torch_cuda):
 
 
 def test_grouped_small_environments_dense(torch_cuda):
-    # environments of at most 96 rows are diagonalised whole (Householder
+    # environments of at most 128 rows are diagonalised whole (Householder
     # reduction, divide and conquer; odd sizes padded to even): D_cut = 8
-    # (n = 64) and 9 (n = 81)
+    # (n = 64), 9 (n = 81), 10 (n = 100) and 11 (n = 121, the largest odd one)
     from paper_2306_00358_amd import Context, hotrg_run, hotrg_run_grouped, make_opts, model_params
 
     cases = [("ising", BETA_C, 0, 8, 20), ("ising", 0.42, 0, 9, 16), ("xy", 1.1, 1, 8, 14),
-             ("potts", math.log(1 + math.sqrt(3)), 0, 9, 12)]
+             ("potts", math.log(1 + math.sqrt(3)), 0, 9, 12), ("ising", 0.43, 0, 10, 12),
+             ("xy", 0.9, 1, 11, 10)]
     P = [model_params(m, beta=b, n_max=nm, q=3) for m, b, nm, _, _ in cases]
     O = [make_opts(d, K, spec_len=6, **(dict(trunc="multiplet", degen_tol=1e-5) if m == "xy" else {}))
          for m, _, _, d, K in cases]
@@ -131,9 +132,16 @@ def test_grouped_small_environments_dense(torch_cuda):
         got, st = hotrg_run_grouped(ctx, P, O, with_steps=True)
         stats = ctx.group_stats()
         alone = [hotrg_run(ctx, p, o) for p, o in zip(P, O)]
-    say("group stats", stats)
-    assert st == [0] * len(cases)
+    with Context(0) as ctx:
+        # D_cut = 10 and 11 alone in a batch: they are swept in lockstep (a
+        # problem that did not join would leave no sweeps) with the same results
+        got2, st2 = hotrg_run_grouped(ctx, P[4:], O[4:])
+        stats2 = ctx.group_stats()
+    say("group stats", stats, stats2)
+    assert st == [0] * len(cases) and st2 == [0, 0]
     assert stats["replays"] >= 5 and stats["fallbacks"] == 0
+    assert stats2["sweeps"] >= 6 and stats2["fallbacks"] == 0
+    assert [g["lnz_per_site"] for g in got2] == [g["lnz_per_site"] for g in got[4:]]
     for (m, b, nm, d, K), o, g, a in zip(cases, O, got, alone):
         T0 = {"ising": lambda: tensors.ising(b), "xy": lambda: tensors.xy(b, nm),
               "potts": lambda: tensors.potts(b, 3)}[m]()
