@@ -44,6 +44,7 @@
 // residuals per check.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -348,13 +349,24 @@ __device__ __forceinline__ void chol_inv_body(const double* __restrict__ G, int 
 // One workgroup of 1024 threads as a 32 x 32 grid; thread (ty, tx) keeps the
 // elements (ty + 32a, tx + 32b), a, b < 4, in registers (p <= 128, a multiple
 // of 16; indices past p are clamped and never published).  Blocks of 8
-// columns: the owners of the block's 8 rows publish them in LDS; every thread
-// the first wave factors the 8 x 8 diagonal block, one element per lane (1/sqrt
-// of a pivot from v_rsq_f64 and two Newton steps), into LDS; after a second barrier
-// thread c < p forms column c of the block's rows of R, into LDS (8 doubles
-// per column) and Rout; after a third every thread takes the rank-8 update.  Only the current block lives in LDS, so four waves per SIMD
-// fit with their register tiles.  *fail is set if a pivot is not positive.
+// columns: the owners of the block's 8 rows publish them in LDS; the first
+// wave factors the 8 x 8 diagonal block, one column per lane, the values of
+// other columns by readlane (1/sqrt of a pivot from v_rsq_f64 and two Newton
+// steps), into LDS; after a second barrier thread c < p forms column c of the
+// block's rows of R, into LDS (8 doubles per column) and Rout; after a third
+// every thread takes the rank-8 update on its register tiles that still
+// matter (not wholly finished, not wholly past p).  Only the current block
+// lives in LDS, so four waves per SIMD fit with their register tiles.  *fail
+// is set if a pivot is not positive.
 constexpr int kCholFThreads = 1024;
+
+// value of v in lane l of the wave (l uniform)
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
 
 __global__ __launch_bounds__(kCholFThreads) void k_chol_factor(const double* __restrict__ G, int p,
                                                                double shift_rel, int scale,
@@ -363,7 +375,8 @@ __global__ __launch_bounds__(kCholFThreads) void k_chol_factor(const double* __r
                                                                int* fail, int* missed) {
   __shared__ double Pb[8 * 128];                 // the block's rows of the working matrix
   __shared__ __align__(16) double Rb[128 * 8];   // the block's rows of R, by column
-  __shared__ double dg[128], dsc[128], red[kCholFThreads / 64], Ls[64], Li[8];
+  __shared__ __align__(16) double Ls[64];
+  __shared__ double dg[128], dsc[128], red[kCholFThreads / 64], Li[8];
   __shared__ int bad;
   const int t = threadIdx.x, tx = t & 31, ty = t >> 5;
   const int pm = p - 1;
@@ -438,26 +451,36 @@ __global__ __launch_bounds__(kCholFThreads) void k_chol_factor(const double* __r
     }
     __syncthreads();
     if (t < 64) {
-      // the 8 x 8 diagonal block, L[r][c] (c >= r) -> R[j0+r][j0+c], one
-      // element per lane of the first wave (lane 8r + c), right-looking
-      const int r0 = t >> 3, c0 = t & 7;
-      double x = c0 >= r0 ? Pb[r0 * 128 + j0 + c0] : 0.0;
+      // the 8 x 8 diagonal block, right-looking, one column per lane (lane
+      // c0 < 8 keeps L[r][c0] -> R[j0+r][j0+c0] in x[r], zeros below the
+      // diagonal; the other lanes repeat columns and are not used); the
+      // pivot and L[r][r2] of another column come from readlane, so no step
+      // waits on LDS
+      const int c0 = t & 7;
+      double x[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) x[r] = r <= c0 ? Pb[r * 128 + j0 + c0] : 0.0;
       bool ok = true;
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
-        const double d = __shfl(x, 9 * r, 64);
+        const double d = readlane_f64(x[r], r);
         ok = ok && d > 0.0;
         const double dd = d > 0.0 ? d : 1.0;
         double y = __builtin_amdgcn_rsq(dd);
         y = fma(y, fma(-0.5 * dd * y, y, 0.5), y);
         y = fma(y, fma(-0.5 * dd * y, y, 0.5), y);
-        if (r0 == r) x = c0 == r ? dd * y : (c0 > r ? x * y : x);
-        if (t == 9 * r) Li[r] = y;
-        const double lc = __shfl(x, 8 * r + c0, 64);  // L[r][c0]
-        const double lr = __shfl(x, 8 * r + r0, 64);  // L[r][r0]
-        if (r0 > r && c0 >= r0) x -= lr * lc;
+        x[r] = c0 == r ? dd * y : (c0 > r ? x[r] * y : x[r]);
+        if (t == r) Li[r] = y;
+#pragma unroll
+        for (int r2 = r + 1; r2 < 8; ++r2) {
+          const double lr = readlane_f64(x[r], r2);  // L[r][r2]
+          if (c0 >= r2) x[r2] -= lr * x[r];
+        }
       }
-      Ls[t] = x;
+      if (t < 8) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) Ls[t * 8 + r] = x[r];  // column t: Ls[c * 8 + r] = L[r][c]
+      }
       if (t == 0 && !ok) bad = 1;
     }
     __syncthreads();
@@ -470,13 +493,13 @@ __global__ __launch_bounds__(kCholFThreads) void k_chol_factor(const double* __r
         for (int r = 0; r < 8; ++r) {
           double w = Pb[r * 128 + t];
 #pragma unroll
-          for (int m = 0; m < r; ++m) w -= Ls[m * 8 + r] * v[m];
+          for (int m = 0; m < r; ++m) w -= Ls[r * 8 + m] * v[m];
           v[r] = w * Li[r];
         }
       } else {
         const int cc = t - j0;
 #pragma unroll
-        for (int r = 0; r < 8; ++r) v[r] = cc >= 0 ? Ls[r * 8 + min(max(cc, 0), 7)] : 0.0;
+        for (int r = 0; r < 8; ++r) v[r] = cc >= 0 ? Ls[min(max(cc, 0), 7) * 8 + r] : 0.0;
       }
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
@@ -490,28 +513,29 @@ __global__ __launch_bounds__(kCholFThreads) void k_chol_factor(const double* __r
       return;  // uniform: every thread read the same flag after the barrier
     }
     // rank-8 update; register rows / columns wholly before j0 + 8 are
-    // finished and skipped (a uniform test), the others take it even where
-    // an element is finished -- nobody reads those again
+    // finished and those wholly past p hold only clamped copies: both are
+    // skipped (uniform tests); the others take it even where an element is
+    // finished -- nobody reads those again
 #pragma unroll
     for (int h = 0; h < 8; h += 4) {  // two rank-4 halves keep the operands few
       double Ri[4][4];
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
-        if (32 * a + 31 < j0 + 8) continue;
+        if (32 * a + 31 < j0 + 8 || 32 * a >= p) continue;
         const int i = min(ty + 32 * a, pm);
 #pragma unroll
         for (int r = 0; r < 4; ++r) Ri[a][r] = Rb[i * 8 + h + r];
       }
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
-        if (32 * b + 31 < j0 + 8) continue;
+        if (32 * b + 31 < j0 + 8 || 32 * b >= p) continue;
         const int k = min(tx + 32 * b, pm);
         double Rk[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) Rk[r] = Rb[k * 8 + h + r];
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
-          if (32 * a + 31 < j0 + 8) continue;
+          if (32 * a + 31 < j0 + 8 || 32 * a >= p) continue;
           double v = A[a][b];
 #pragma unroll
           for (int r = 0; r < 4; ++r) v -= Ri[a][r] * Rk[r];
@@ -898,14 +922,20 @@ static inline int splitk_chunk(int K) {
   return c < 16 ? 16 : c;
 }
 
-// K chunk of the block products V M (p x n times n x n): four partial
-// products, so that p = 128 rows still give 4 x 2 x (n / 64) workgroups
-static inline int vm_chunk(int n) { return ((n + 3) / 4 + 15) / 16 * 16; }
+// K chunk of the block products V M (p x n times n x n) by 64 x 64 tiles:
+// enough partial products for about 512 workgroups (at least 4, at most
+// 16), so that p = 128, n = 4096 takes 4 x 2 x 64 and p = 64, n = 1024 takes
+// 16 x 1 x 16 instead of 64 workgroups that would leave most of the chip idle
+static inline int vm_chunk(int n, int p) {
+  const int tiles = ((p + 63) / 64) * ((n + 63) / 64);
+  const int parts = std::min(16, std::max(4, (512 + tiles - 1) / tiles));
+  return ((n + parts - 1) / parts + 15) / 16 * 16;
+}
 
 static inline size_t partial_doubles(int n, int p) {
   const size_t pn = (size_t)p * n, pp = (size_t)p * p;
   const size_t gram = (size_t)((n + splitk_chunk(n) - 1) / splitk_chunk(n)) * pp;
-  const size_t vm = (size_t)((n + vm_chunk(n) - 1) / vm_chunk(n)) * pn;
+  const size_t vm = (size_t)((n + vm_chunk(n, p) - 1) / vm_chunk(n, p)) * pn;
   return gram > vm ? gram : vm;
 }
 
@@ -938,7 +968,7 @@ bool topk_eigs(const double* M, int n, int p, int need, double tol,
                int* dinfo, int* iters, int* enough, double* resid, hipStream_t s) {
   const size_t pn = (size_t)p * n, pp = (size_t)p * p;
   const int kc = splitk_chunk(n);
-  const int kv = vm_chunk(n);
+  const int kv = vm_chunk(n, p);
   double* V = ws;
   double* Y = V + pn;
   double* T2 = Y + pn;

@@ -139,7 +139,7 @@ size_t footprint_of(const hotrg_model_params* p, const hotrg_opts* o_in) {
     need("U", 3 * n * dn * 8);
     const int p = std::min(128, std::max(2 * dn, dn + 17));
     need("eig", (double)topk_workspace_doubles((int)n, (p + 15) / 16 * 16) * 8 + (double)p * n * 8);
-    need("dense", n >= 1024 ? n * n * 8 : 0);  // dsyevd fallback workspace
+    need("dense", n > 128 ? n * n * 8 : 0);  // dsyevd fallback workspace
     if (o->isometry == HOTRG_ISO_TWO_SIDED && dn < n) {
       // mirrored operands, right environment, its eigenpairs
       need("side", 2.0 * dx * dy * dx * dy * 8 + n * n * 8 + n * 8 + (double)p * n * 8);

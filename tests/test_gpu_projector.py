@@ -2,7 +2,8 @@
 and isometry of Sec. 2) against the oracle's projector (an SVD of M) on
 environments of three kinds: one from an oracle coarse-graining run (Ising at
 T_c, D = 32, n = 1024, block subspace iteration), graded synthetic ones
-(n = 2304 and 4096, blocks of 96 and 128 vectors; n = 576, the dense solver),
+(n = 2304, 4096, 576 and 256, blocks of 96, 128, 64 and 64 vectors; n = 400
+with 60 kept, the dense solver),
 ones with exactly equal groups of eigenvalues all through the block (the
 deflation of the Rayleigh-Ritz divide and conquer) and one with an exactly
 degenerate pair at the cut (multiplet rule).
@@ -99,18 +100,20 @@ def test_projector_of_an_oracle_ising_environment(torch_cuda):
         _check(torch_cuda, ctx, M, 32, spec_len=40, label="ising T_c step 8", iterative=True)
 
 
-@pytest.mark.parametrize("n, d_new, rank, decay, seed", [
-    (2304, 48, 320, 10.0, 11),   # block of 96 vectors
-    (4096, 64, 384, 12.0, 12),   # block of 128 vectors (the D = 64 shape)
-    (576, 24, 200, 9.0, 13),     # n < 1024: the dense solver
+@pytest.mark.parametrize("n, d_new, rank, decay, seed, iterative", [
+    (2304, 48, 320, 10.0, 11, True),   # block of 96 vectors
+    (4096, 64, 384, 12.0, 12, True),   # block of 128 vectors (the D = 64 shape)
+    (576, 24, 200, 9.0, 13, True),     # block of 64 vectors, a ninth of n
+    (256, 24, 120, 8.0, 17, True),     # block of 64 vectors, a quarter of n
+    (400, 60, 200, 9.0, 18, False),    # 128 vectors not small against n: dense
 ])
-def test_projector_of_graded_environments(torch_cuda, n, d_new, rank, decay, seed):
+def test_projector_of_graded_environments(torch_cuda, n, d_new, rank, decay, seed, iterative):
     from paper_2306_00358_amd import Context
 
     M = graded_gram(n, rank, decay, seed)
     with Context(0) as ctx:
         _check(torch_cuda, ctx, M, d_new, spec_len=d_new + 16, label="graded",
-               iterative=n >= 1024)
+               iterative=iterative)
 
 
 def test_projector_multiplet_cut_at_a_degenerate_pair(torch_cuda):
