@@ -517,6 +517,15 @@ bool gemm_f64_syrk(const double* A, long long lda, double* C, const OutMap& om, 
                    hipStream_t s, const double* A_2, double* C_2) {
   if (M < 128 || (long long)M * M < (1LL << 20) || K < 16 || K % 16 != 0) return false;
   if ((lda & 1) || ((uintptr_t)A & 15) || ((uintptr_t)A_2 & 15)) return false;
+  // the symmetric grid (256 x 128 tiles reaching the upper triangle) must
+  // fill at least half of the 256 compute units: below that (M = 1024: 40
+  // workgroups for both products, each with the whole K loop) the two full
+  // products with their many smaller tiles take less time despite twice the
+  // MFMAs
+  const int nbn = (M + 127) / 128;
+  int tiles = 0;
+  for (int bm = 0; bm * 256 < M; ++bm) tiles += nbn - 2 * bm;
+  if ((A_2 ? 2 : 1) * tiles < 128) return false;
   launch_lds<4, 2, 16, GEMM_TAG_ENV, 3>(A, lda, A, lda, B_KCONTIG, C, om, M, M, K, nullptr, s,
                                         A_2 ? 2 : 1, A_2, C_2);
   return true;
