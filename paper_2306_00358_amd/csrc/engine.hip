@@ -539,14 +539,14 @@ void reserve_records(hotrg_ctx* c, hotrg_state* st, int k, int spec_len) {
 // Block size of the iterative eigensolve for d_new leading pairs of an n x n
 // environment; whether it applies (else the dense solver runs: the two-launch
 // one up to n = 128, rocSOLVER above, where a block of p >= need + 16 vectors
-// would not be small against n).
+// would exceed half of n).
 static bool eig_block(int n, int dn, int spec_len, int eig_mode, int* need_out, int* p_out) {
   const int need = std::max(dn + 1, std::min(spec_len, n));
   int p = std::min(128, std::max(2 * dn, need + 16));
   p = (p + 15) / 16 * 16;
   *need_out = need;
   *p_out = p;
-  return eig_mode == HOTRG_EIG_AUTO && n > 128 && need + 16 <= p && p <= 128 && p * 4 <= n;
+  return eig_mode == HOTRG_EIG_AUTO && n > 128 && need + 16 <= p && p <= 128 && p * 2 <= n;
 }
 
 // Leading eigenpairs of the symmetric n x n matrix in Mb: eigenvalues

@@ -2,8 +2,8 @@
 and isometry of Sec. 2) against the oracle's projector (an SVD of M) on
 environments of three kinds: one from an oracle coarse-graining run (Ising at
 T_c, D = 32, n = 1024, block subspace iteration), graded synthetic ones
-(n = 2304, 4096, 576 and 256, blocks of 96, 128, 64 and 64 vectors; n = 400
-with 60 kept, the dense solver),
+(n = 2304, 4096, 576, 256 and 400, blocks of 96, 128, 64, 64 or 128 and 128
+vectors; n = 200 with 60 kept, the dense solver),
 ones with exactly equal groups of eigenvalues all through the block (the
 deflation of the Rayleigh-Ritz divide and conquer) and one with an exactly
 degenerate pair at the cut (multiplet rule).
@@ -105,7 +105,9 @@ def test_projector_of_an_oracle_ising_environment(torch_cuda):
     (4096, 64, 384, 12.0, 12, True),   # block of 128 vectors (the D = 64 shape)
     (576, 24, 200, 9.0, 13, True),     # block of 64 vectors, a ninth of n
     (256, 24, 120, 8.0, 17, True),     # block of 64 vectors, a quarter of n
-    (400, 60, 200, 9.0, 18, False),    # 128 vectors not small against n: dense
+    (256, 64, 200, 12.0, 19, True),    # block of 128 vectors, half of n (a D_cut = 64 warm-up step)
+    (400, 60, 200, 9.0, 18, True),     # block of 128 vectors
+    (200, 60, 150, 9.0, 20, False),    # 128 vectors more than half of n: dense
 ])
 def test_projector_of_graded_environments(torch_cuda, n, d_new, rank, decay, seed, iterative):
     from paper_2306_00358_amd import Context
