@@ -394,8 +394,10 @@ __global__ __launch_bounds__(512) void k_gemm_rp_grouped(const RpItem* __restric
   const RpItem& it = items[g];
   if (it.gate && *it.gate == 0) return;
   const int local = blockIdx.x - begin[g];
+  const int tm = (it.M + 255) / 256, tn = (it.N + BN - 1) / BN;
+  if (local >= tm * tn) return;  // padding of the item's range to a multiple of 8
   int im, in;
-  tile_order((it.M + 255) / 256, (it.N + BN - 1) / BN, local, 4, im, in);
+  tile_order(tm, tn, local, 4, im, in);
   rp_tile<MODE, OUT, TM, BN, NST>(it.A.hi, it.A.lo, it.lda, it.B.hi, it.B.lo, it.ldb, it.C,
                                   it.Clo, it.om, it.M, it.N, it.K, it.maxbits, im * 256, in * BN);
 }
@@ -485,8 +487,11 @@ static void launch_rp_tag(int tag, const RpOperand& A, long long lda, const RpOp
 
 // ---- grouped launch ----
 int rp_group_tiles(const RpItem& it, int cfg) {
+  // rounded up to a multiple of 8, so that every item's range starts on a
+  // multiple of 8 and the XCD-grouped tile order sees blockIdx % 8 as the XCD
+  // (the workgroups past the item's tiles return at once)
   const int bn = cfg == 0 ? 256 : 128;
-  return ((it.M + 255) / 256) * ((it.N + bn - 1) / bn);
+  return (((it.M + 255) / 256) * ((it.N + bn - 1) / bn) + 7) / 8 * 8;
 }
 
 template <int MODE, int OUT, int TM, int BN, int NST>

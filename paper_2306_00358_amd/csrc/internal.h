@@ -148,8 +148,9 @@ struct RpItem {
   unsigned long long* maxbits;
   const int* gate;
 };
-// Output tiles of an item under tile configuration cfg (0: 256 x 256,
-// 1: 256 x 128 two stages, 2: 256 x 128 three stages).
+// Workgroups of an item under tile configuration cfg (0: 256 x 256,
+// 1: 256 x 128 two stages, 2: 256 x 128 three stages): its output tiles,
+// rounded up to a multiple of 8.
 int rp_group_tiles(const RpItem& it, int cfg);
 // One launch over `tiles` tiles; d_begin[i] is the first tile of item i
 // (ascending, d_begin[0] = 0).  Requirements per item as for gemm_rp.
