@@ -27,6 +27,7 @@ steps of the timed runs comes from HIP events recorded on the library's
 stream around each phase.
 
     python bench.py --batch             # 64 XY problems on the worker pool
+    python bench.py --batch --batch-engine lockstep   # ... in lockstep (grouped launches)
     python bench.py --serve N [--serve-loads 0.8,0.5,1.0,1.2]
 
 `--serve` replays a seeded stream of N mixed requests at Poisson arrival
@@ -86,6 +87,8 @@ def parse():
                          "saturation rate; the stream at the first one is the result, "
                          "the others are reported under load_sweep")
     ap.add_argument("--workers", type=int, default=16)
+    ap.add_argument("--batch-engine", choices=["pool", "lockstep"], default="pool",
+                    help="with --batch: the worker pool (and one stream), or the lockstep engine")
     ap.add_argument("--kernel-probe", action="store_true",
                     help="run one coarse contraction at the benchmark shape and a 1 GiB "
                          "calibration copy (for hardware-counter runs), then exit")
@@ -150,6 +153,29 @@ def run_batch_bench(args):
     flops = sum(sum(step_flops(*d)["total"] for d in dims_schedule(2 * p.n_max + 1, o.d_cut, o.n_steps))
                 for p, o in probs)
     n_dir = sum(o.n_steps for o in O)
+    config = {"workload": "64 XY problems, beta in [0.8,1.4], n_max 3..6, D_cut in "
+                          "{24,32,40,48}, 25 directional steps, %s contractions" % prec}
+
+    if args.batch_engine == "lockstep":
+        from paper_2306_00358_amd import hotrg_run_grouped
+
+        with Context(0) as ctx:
+            hotrg_run_grouped(ctx, P, O)  # warm-up: tile choices, workspaces, graphs
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res, st = hotrg_run_grouped(ctx, P, O)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            stats = ctx.group_stats()
+        assert st == [0] * len(P), st
+        print(json.dumps({
+            "metric": METRIC + " [XY batch, lockstep]", "value": n_dir / dt, "unit": "steps/s",
+            "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": dt * 1e3,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": DTYPE[prec], "data": "synthetic", "config": config,
+            "tflops": flops / dt / 1e12, "graph": stats,
+            "lnz_per_site": [r["lnz_per_site"] for r in res]}), flush=True)
+        return
 
     def timed(workers):
         with Context(0) as ctx:
@@ -174,9 +200,7 @@ def run_batch_bench(args):
         "ms_per_step": t_pool * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": DTYPE[prec], "data": "synthetic",
-        "config": {"workload": "64 XY problems, beta in [0.8,1.4], n_max 3..6, D_cut in "
-                               "{24,32,40,48}, 25 directional steps, %s contractions" % prec,
-                   "workers": args.workers},
+        "config": dict(config, workers=args.workers),
         "tflops": flops / t_pool / 1e12,
         "sequential_steps_per_s": n_dir / t_seq,
         "speedup_vs_sequential": t_seq / t_pool,
