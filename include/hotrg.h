@@ -251,13 +251,16 @@ hotrg_status hotrg_run_batch(hotrg_ctx* ctx, int n, const hotrg_model_params* pa
  * directional step per sweep, each phase of the sweep one launch over every
  * problem -- grouped MFMA GEMMs reading a device table of the problems'
  * products (uneven D_cut and shapes), a batched block eigensolver (subspace
- * iteration with a fixed budget of rounds, Rayleigh-Ritz by a parallel Jacobi
- * method, one workgroup per problem), batched bookkeeping -- and the whole
+ * iteration with a fixed budget of rounds, Rayleigh-Ritz by Householder
+ * reduction and divide and conquer, one workgroup per problem; environments of
+ * at most 128 rows diagonalised whole by the same two kernels), batched
+ * bookkeeping -- and the whole
  * sweep is captured once as a HIP graph and replayed (captured again when a
  * problem has finished its steps).  Grouped launches pick their tile shapes by
  * timing the candidates on the first sweep of a set of shapes.  A problem
  * joins the batch when its steady state has D' + 17 <= p <= 128 and 4p <= D'^2
- * (p = the eigensolver's block size, about 2 D'), the one-sided isometry, the
+ * (p = the eigensolver's block size, about 2 D') or D'^2 <= 128 (all problems
+ * of a batch alike in this), the one-sided isometry, the
  * automatic eigensolver choice and the batch's steady precision; other
  * problems run whole, one after another, before the batch.  A problem whose
  * batched eigensolve does not converge within the budget is run again alone.
