@@ -346,9 +346,10 @@ __device__ __forceinline__ void chol_inv_body(const double* __restrict__ G, int 
 // G + s I, s = shift_rel * trace of the matrix factored, into Rout (p x p
 // row-major, zeros below the diagonal) and D^-1 (ones without `scale`) into
 // Rout + p * p; with identity_tol > 0 and G the identity to within it, R = I.
-// One workgroup of 1024 threads as a 32 x 32 grid; thread (ty, tx) keeps the
-// elements (ty + 32a, tx + 32b), a, b < 4, in registers (p <= 128, a multiple
-// of 16; indices past p are clamped and never published).  Blocks of 8
+// One workgroup of GW x GW threads (GW = 32 for p <= 128, 16 for p <= 64:
+// the same register tiles, and barriers over 4 waves instead of 16); thread
+// (ty, tx) keeps the elements (ty + GW a, tx + GW b), a, b < 4, in registers
+// (p a multiple of 16; indices past p are clamped and never published).  Blocks of 8
 // columns: the owners of the block's 8 rows publish them in LDS; the first
 // wave factors the 8 x 8 diagonal block, one column per lane, the values of
 // other columns by readlane (1/sqrt of a pivot from v_rsq_f64 and two Newton
@@ -358,7 +359,6 @@ __device__ __forceinline__ void chol_inv_body(const double* __restrict__ G, int 
 // matter (not wholly finished, not wholly past p).  Only the current block
 // lives in LDS, so four waves per SIMD fit with their register tiles.  *fail
 // is set if a pivot is not positive.
-constexpr int kCholFThreads = 1024;
 
 // value of v in lane l of the wave (l uniform)
 __device__ __forceinline__ double readlane_f64(double v, int l) {
@@ -368,7 +368,8 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-__global__ __launch_bounds__(kCholFThreads) void k_chol_factor(const double* __restrict__ G, int p,
+template <int GW>
+__global__ __launch_bounds__(GW * GW) void k_chol_factor(const double* __restrict__ G, int p,
                                                                double shift_rel, int scale,
                                                                double identity_tol,
                                                                double* __restrict__ Rout,
@@ -376,16 +377,16 @@ __global__ __launch_bounds__(kCholFThreads) void k_chol_factor(const double* __r
   __shared__ double Pb[8 * 128];                 // the block's rows of the working matrix
   __shared__ __align__(16) double Rb[128 * 8];   // the block's rows of R, by column
   __shared__ __align__(16) double Ls[64];
-  __shared__ double dg[128], dsc[128], red[kCholFThreads / 64], Li[8];
+  __shared__ double dg[128], dsc[128], red[GW * GW / 64], Li[8];
   __shared__ int bad;
-  const int t = threadIdx.x, tx = t & 31, ty = t >> 5;
+  const int t = threadIdx.x, tx = t % GW, ty = t / GW;
   const int pm = p - 1;
   double A[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-      const int i = min(ty + 32 * a, pm), k = min(tx + 32 * b, pm);
+      const int i = min(ty + GW * a, pm), k = min(tx + GW * b, pm);
       A[a][b] = G[min(i, k) * p + max(i, k)];  // upper part, mirrored
     }
   if (identity_tol > 0.0) {
@@ -394,16 +395,16 @@ __global__ __launch_bounds__(kCholFThreads) void k_chol_factor(const double* __r
     for (int a = 0; a < 4; ++a)
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
-        const int i = ty + 32 * a, k = tx + 32 * b;
+        const int i = ty + GW * a, k = tx + GW * b;
         if (i < p && k < p) d = fmax(d, fabs(A[a][b] - (i == k ? 1.0 : 0.0)));
       }
     for (int o = 32; o > 0; o >>= 1) d = fmax(d, __shfl_xor(d, o, 64));
     if ((t & 63) == 0) red[t >> 6] = d;
     __syncthreads();
     double mx = 0.0;
-    for (int w = 0; w < kCholFThreads / 64; ++w) mx = fmax(mx, red[w]);
+    for (int w = 0; w < GW * GW / 64; ++w) mx = fmax(mx, red[w]);
     if (mx <= identity_tol) {  // uniform: every thread reduced the same values
-      for (int e = t; e < p * p; e += kCholFThreads) Rout[e] = (e / p == e % p) ? 1.0 : 0.0;
+      for (int e = t; e < p * p; e += GW * GW) Rout[e] = (e / p == e % p) ? 1.0 : 0.0;
       if (t < p) Rout[p * p + t] = 1.0;
       return;
     }
@@ -412,7 +413,7 @@ __global__ __launch_bounds__(kCholFThreads) void k_chol_factor(const double* __r
   if (tx == ty) {
 #pragma unroll
     for (int a = 0; a < 4; ++a)
-      if (ty + 32 * a < p) dg[ty + 32 * a] = A[a][a];
+      if (ty + GW * a < p) dg[ty + GW * a] = A[a][a];
   }
   if (t == 0) bad = 0;
   __syncthreads();
@@ -427,9 +428,9 @@ __global__ __launch_bounds__(kCholFThreads) void k_chol_factor(const double* __r
   if (scale) {
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-      const double dr = dsc[min(ty + 32 * a, pm)];
+      const double dr = dsc[min(ty + GW * a, pm)];
 #pragma unroll
-      for (int b = 0; b < 4; ++b) A[a][b] *= dr * dsc[min(tx + 32 * b, pm)];
+      for (int b = 0; b < 4; ++b) A[a][b] *= dr * dsc[min(tx + GW * b, pm)];
     }
   }
   const double shift = shift_rel * tr;
@@ -440,13 +441,13 @@ __global__ __launch_bounds__(kCholFThreads) void k_chol_factor(const double* __r
 
   const int nblk = p >> 3;
   for (int J = 0; J < nblk; ++J) {
-    const int j0 = 8 * J, aj = j0 >> 5, tj = j0 & 31;
+    const int j0 = 8 * J, aj = j0 / GW, tj = j0 % GW;
     if (ty >= tj && ty < tj + 8) {
 #pragma unroll
       for (int a = 0; a < 4; ++a)
         if (a == aj) {
 #pragma unroll
-          for (int b = 0; b < 4; ++b) Pb[(ty - tj) * 128 + tx + 32 * b] = A[a][b];
+          for (int b = 0; b < 4; ++b) Pb[(ty - tj) * 128 + tx + GW * b] = A[a][b];
         }
     }
     __syncthreads();
@@ -521,21 +522,21 @@ __global__ __launch_bounds__(kCholFThreads) void k_chol_factor(const double* __r
       double Ri[4][4];
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
-        if (32 * a + 31 < j0 + 8 || 32 * a >= p) continue;
-        const int i = min(ty + 32 * a, pm);
+        if (GW * a + GW - 1 < j0 + 8 || GW * a >= p) continue;
+        const int i = min(ty + GW * a, pm);
 #pragma unroll
         for (int r = 0; r < 4; ++r) Ri[a][r] = Rb[i * 8 + h + r];
       }
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
-        if (32 * b + 31 < j0 + 8 || 32 * b >= p) continue;
-        const int k = min(tx + 32 * b, pm);
+        if (GW * b + GW - 1 < j0 + 8 || GW * b >= p) continue;
+        const int k = min(tx + GW * b, pm);
         double Rk[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) Rk[r] = Rb[k * 8 + h + r];
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
-          if (32 * a + 31 < j0 + 8 || 32 * a >= p) continue;
+          if (GW * a + GW - 1 < j0 + 8 || GW * a >= p) continue;
           double v = A[a][b];
 #pragma unroll
           for (int r = 0; r < 4; ++r) v -= Ri[a][r] * Rk[r];
@@ -1012,9 +1013,13 @@ bool topk_eigs(const double* M, int n, int p, int need, double tol,
     const int last = full ? 2 : (check ? 1 : 0);
     for (int pass = 0; pass <= last; ++pass) {
       gemm_f64_splitk(src, n, src, n, B_KCONTIG, G, p, p, p, n, kc, part, s);
-      hipLaunchKernelGGL(k_chol_factor, dim3(1), dim3(kCholFThreads), 0, s, G, p,
-                         pass < 2 ? shift_rel : 0.0, pass < 2 ? 1 : 0,
-                         (pass == 0 || full) ? 0.0 : 1e-2, Rf, fail, fail + 1);
+      const double sh = pass < 2 ? shift_rel : 0.0, itol = (pass == 0 || full) ? 0.0 : 1e-2;
+      if (p <= 64)
+        hipLaunchKernelGGL(k_chol_factor<16>, dim3(1), dim3(256), 0, s, G, p, sh,
+                           pass < 2 ? 1 : 0, itol, Rf, fail, fail + 1);
+      else
+        hipLaunchKernelGGL(k_chol_factor<32>, dim3(1), dim3(1024), 0, s, G, p, sh,
+                           pass < 2 ? 1 : 0, itol, Rf, fail, fail + 1);
       double* dst = (pass == last) ? Vout : (src == T2 ? Y : T2);
       if (dst == src) dst = (src == Y) ? T2 : Y;
       hipLaunchKernelGGL(k_trsm_rows, dim3((n + kTrsmCols - 1) / kTrsmCols), dim3(256), trsm_lds,
