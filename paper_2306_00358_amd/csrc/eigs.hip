@@ -683,6 +683,10 @@ void launch_chol_inv_batched(const CholItem* d_items, int count, int pmax, int p
 // tridiagonal solver expects; d (p) and e (p - 1) receive the tridiagonal.
 // Every loop has a fixed trip count and every sum a fixed order.
 constexpr int kTrdThreads = 1024;
+// threads of a launch for p rows: the 8 lanes of every row below p, whole
+// waves, at least 128 (the threads that clear the 128-entry vectors); fewer
+// waves than 1024 threads for small p make every barrier cheaper
+static inline int trd_threads(int p) { return std::max(128, (8 * p + 63) / 64 * 64); }
 
 // another lane of the same 8-lane group (DPP: quad_perm [1,0,3,2],
 // quad_perm [2,3,0,1], row_half_mirror); every lane of the group is active
@@ -842,7 +846,7 @@ bool dense_eig_small(double* M, int n, double* W, double* E, int* info, hipStrea
                                             (int)((size_t)128 * 128 * sizeof(double))) ==
                         hipSuccess;
   if (!lds_set || n < 3 || n > 128) return false;
-  hipLaunchKernelGGL(k_sytrd_small, dim3(1), dim3(kTrdThreads), (size_t)128 * n * sizeof(double),
+  hipLaunchKernelGGL(k_sytrd_small, dim3(1), dim3(trd_threads(n)), (size_t)128 * n * sizeof(double),
                      s, M, n, W, E);
   return tridiag_eig_small_back(W, E, n, W, M, info, s);
 }
@@ -862,7 +866,7 @@ void group_sytrd(const GroupStep* d, int count, int pmax, hipStream_t s) {
                                             (int)((size_t)128 * 128 * sizeof(double))) ==
                         hipSuccess;
   (void)lds_set;
-  hipLaunchKernelGGL(k_group_sytrd, dim3(count), dim3(kTrdThreads),
+  hipLaunchKernelGGL(k_group_sytrd, dim3(count), dim3(trd_threads(pmax)),
                      (size_t)128 * pmax * sizeof(double), s, d);
 }
 
@@ -1053,7 +1057,7 @@ bool topk_eigs(const double* M, int n, int p, int need, double tol,
     // tridiagonal form and its reduction matrix (H = Q^T, row-major) in one
     // workgroup, then divide and conquer on the tridiagonal in another
     // (Z^T into Rt, eigenvalues over its diagonal in W)
-    hipLaunchKernelGGL(k_sytrd_small, dim3(1), dim3(kTrdThreads),
+    hipLaunchKernelGGL(k_sytrd_small, dim3(1), dim3(trd_threads(p)),
                        (size_t)128 * p * sizeof(double), s, H, p, W, E);
     if (!tridiag_eig_small(W, E, p, W, Rt, dinfo, s)) return false;
     // Ritz vectors of H as rows: G = Z^T Q^T
