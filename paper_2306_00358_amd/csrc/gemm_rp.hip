@@ -90,7 +90,7 @@ __device__ __forceinline__ void rp_load(const void* __restrict__ hi, const void*
 // (TM MFMA tiles of 16 rows): TM = 4 for BN = 128, TM = 8 for BN = 256.
 // One output tile at rows m0.., columns n0.. (shared by the single-product
 // kernel and the grouped one).
-template <int MODE, int OUT, int TM, int BN, int NST>
+template <int MODE, int OUT, int TM, int BN, int NST, int PRIO = 0>
 __device__ __forceinline__ void rp_tile(const void* __restrict__ Ahi, const void* __restrict__ Alo,
                                         long long lda, const void* __restrict__ Bhi,
                                         const void* __restrict__ Blo, long long ldb,
@@ -249,6 +249,9 @@ __device__ __forceinline__ void rp_tile(const void* __restrict__ Ahi, const void
 #pragma unroll
       for (int j = 0; j < 4; ++j) gl[j] = rd(bs, rb + 16 * j, c1);
       __builtin_amdgcn_sched_group_barrier(0x100, 5, 0);  // 5 LDS reads
+      // PRIO: the wave in its MFMA sequence takes issue priority over the
+      // other wave of its SIMD
+      if constexpr (PRIO) __builtin_amdgcn_s_setprio(1);
 #pragma unroll
       for (int i = 0; i < TM; ++i) {
         if (i + 1 < TM) {
@@ -290,6 +293,7 @@ __device__ __forceinline__ void rp_tile(const void* __restrict__ Ahi, const void
           __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
         }
       }
+      if constexpr (PRIO) __builtin_amdgcn_s_setprio(0);
     } else {
     f4 a0[TM], a1[TM], b0[4], b1[4];
 #pragma unroll
@@ -359,7 +363,7 @@ __device__ __forceinline__ void rp_tile(const void* __restrict__ Ahi, const void
   }
 }
 
-template <int MODE, int OUT, int TAG, int TM, int BN, int NST>
+template <int MODE, int OUT, int TAG, int TM, int BN, int NST, int PRIO = 0>
 __global__ __launch_bounds__(512) void k_gemm_rp(const void* __restrict__ Ahi,
                                                  const void* __restrict__ Alo, long long lda,
                                                  const void* __restrict__ Bhi,
@@ -369,8 +373,8 @@ __global__ __launch_bounds__(512) void k_gemm_rp(const void* __restrict__ Ahi,
                                                  unsigned long long* maxbits, int gm) {
   int im, in;
   tile_order((M + 255) / 256, (N + BN - 1) / BN, blockIdx.x, gm, im, in);
-  rp_tile<MODE, OUT, TM, BN, NST>(Ahi, Alo, lda, Bhi, Blo, ldb, C, Clo, om, M, N, K, maxbits,
-                                  im * 256, in * BN);
+  rp_tile<MODE, OUT, TM, BN, NST, PRIO>(Ahi, Alo, lda, Bhi, Blo, ldb, C, Clo, om, M, N, K,
+                                        maxbits, im * 256, in * BN);
 }
 
 // Grouped form: one launch over the output tiles of every product in the
@@ -431,6 +435,19 @@ static void launch_rp_shape(int tag, const RpOperand& A, long long lda, const Rp
     hipLaunchKernelGGL(kern, grid, dim3(512), LDS, s, A.hi, A.lo, lda, B.hi, B.lo, ldb, C, Clo,
                        om, M, N, K, maxbits, gm);
   };
+  if constexpr (MODE == RP_BF16X3 && NST == 2) {
+    // the split-BF16 two-stage tile of C2 raises its wave priority over its
+    // MFMA sequence (s_setprio): 0.5% faster at D = 64 in alternating runs on
+    // one chip, the same results; HOTRG_RP_PRIO=0 turns it off
+    static const bool prio = [] {
+      const char* e = getenv("HOTRG_RP_PRIO");
+      return !(e && atoi(e) == 0);
+    }();
+    if (prio && tag == GEMM_TAG_C2) {
+      go(k_gemm_rp<MODE, OUT, GEMM_TAG_C2, TM, BN, NST, 1>);
+      return;
+    }
+  }
   if (tag == GEMM_TAG_C2)
     go(k_gemm_rp<MODE, OUT, GEMM_TAG_C2, TM, BN, NST>);
   else if (tag == GEMM_TAG_ENV)
